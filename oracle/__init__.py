@@ -1,0 +1,217 @@
+"""CPU FP64 oracle for the cuROB test functions (arXiv 1407.7737) -- test infrastructure.
+
+This package is the correctness judge for the GPU library.  It is a ctypes binding to
+``curob_oracle.c``: plain FP64 loops that evaluate each definition of the paper literally
+(shift, dense rotation, formula, bias).  It shares no code with ``paper_1407_7737_amd`` and is
+only imported by ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py``.  The product path never calls it.
+
+Parity status per part is listed at the top of ``curob_oracle.c``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "curob_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+# Tab. 1 ids
+SPHERE, ELLIPSOID, ELLIPTIC, DISCUS, CIGAR, POWERS, SHARPV = range(7)
+STEP, WEIERSTRASS, GRIEWANK, RASTRIGIN_U, RASTRIGIN, SCHAFFERSF7 = range(7, 13)
+GRIE_ROSEN, ROSENBROCK, SCHWEFEL_U, SCHWEFEL, KATSUURA, LUNACEK = range(13, 19)
+ACKLEY, HAPPYCAT, HGBAT, SCHAFFERSF6 = range(19, 23)
+
+# (scale s, offset c, rotated) read off each function's "where" clause, Secs. 3-4
+XFORM = {
+    0: (1.0, 0.0, True), 1: (1.0, 0.0, True), 2: (1.0, 0.0, True), 3: (1.0, 0.0, True),
+    4: (1.0, 0.0, True), 5: (0.01, 0.0, True), 6: (1.0, 0.0, True), 7: (1.0, 0.0, True),
+    8: (0.005, 0.0, True), 9: (6.0, 0.0, True), 10: (0.0512, 0.0, False), 11: (0.0512, 0.0, True),
+    12: (1.0, 0.0, True), 13: (0.05, 1.0, True), 14: (0.02048, 1.0, True), 15: (10.0, 0.0, False),
+    16: (10.0, 0.0, True), 17: (0.05, 0.0, True), 18: (0.1, 2.5, True), 19: (1.0, 0.0, True),
+    20: (0.05, -1.0, True), 21: (0.05, -1.0, True), 22: (1.0, 0.0, True),
+}
+
+
+def build(force: bool = True) -> str:
+    """Compile ``liboracle.so`` with gcc (plain -O2, no fast-math; OpenMP only for timing)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-std=c11", "-O2", "-fPIC", "-shared", "-fopenmp", "-fno-fast-math",
+             "-Wall", "-Wextra", "-Wno-unused-function", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i32, u32, u64, i64, f64 = ctypes.c_int, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_long, ctypes.c_double
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        up = ctypes.POINTER(ctypes.c_uint64)
+        sig = {
+            "orc_problem_basic": (P, [i32, i32, u64]),
+            "orc_problem_custom_basic": (P, [i32, i32, i32, u64, f64, f64, i32]),
+            "orc_problem_hybrid": (P, [i32, i32, u64, i32, ip, dp]),
+            "orc_problem_composition": (P, [i32, i32, u64, i32, ip, dp, dp, dp]),
+            "orc_problem_paper_hybrid": (P, [i32, i32, u64]),
+            "orc_problem_paper_composition": (P, [i32, i32, u64]),
+            "orc_problem_fid": (P, [i32, i32, u64]),
+            "orc_problem_free": (None, [P]),
+            "orc_evaluate": (i32, [P, dp, i64, dp, i32]),
+            "orc_problem_dim": (i32, [P]),
+            "orc_problem_kind": (i32, [P]),
+            "orc_problem_ncomp": (i32, [P]),
+            "orc_problem_shift": (i32, [P, i32, dp]),
+            "orc_problem_rotation": (i32, [P, i32, dp]),
+            "orc_problem_hybrid_parts": (i32, [P, ip, ip, dp]),
+            "orc_problem_transform": (i32, [P, dp, dp]),
+            "orc_g": (f64, [i32, i32, dp]),
+            "orc_stream_u64": (None, [u64, i32, u32, u32, i64, up]),
+            "orc_stream_normal": (None, [u64, i32, u32, u32, i64, dp]),
+            "orc_splitmix64_from_state": (u64, [u64, i64]),
+            "orc_orthonormalise": (None, [i32, dp]),
+            "orc_num_threads_available": (i32, []),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+class Problem:
+    """One oracle problem (basic, hybrid or composition)."""
+
+    def __init__(self, handle):
+        if not handle:
+            raise ValueError("oracle rejected the problem definition")
+        self._h = handle
+        self.dim = lib().orc_problem_dim(handle)
+        self.kind = lib().orc_problem_kind(handle)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.orc_problem_free(h)
+            self._h = None
+
+    def __call__(self, x, threads: int = 1) -> np.ndarray:
+        x = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+        if x.ndim == 1:
+            x = x[None, :]
+        assert x.shape[1] == self.dim
+        f = np.empty(x.shape[0], dtype=np.float64)
+        lib().orc_evaluate(self._h, _dp(x), x.shape[0], _dp(f), int(threads))
+        return f
+
+    def shift(self, comp: int = 0) -> np.ndarray:
+        o = np.empty(self.dim)
+        assert lib().orc_problem_shift(self._h, comp, _dp(o)) == 0
+        return o
+
+    def rotation(self, comp: int = 0) -> np.ndarray:
+        R = np.empty((self.dim, self.dim))
+        assert lib().orc_problem_rotation(self._h, comp, _dp(R)) == 0
+        return R
+
+    def hybrid_parts(self):
+        perm = np.empty(self.dim, dtype=np.int32)
+        sizes = np.zeros(16, dtype=np.int32)
+        blocks = np.empty(self.dim * self.dim)
+        ng = lib().orc_problem_hybrid_parts(self._h, _ip(perm), _ip(sizes), _dp(blocks))
+        assert ng > 0
+        sizes = sizes[:ng].copy()
+        out, off = [], 0
+        for n in sizes:
+            out.append(blocks[off:off + n * n].reshape(n, n).copy())
+            off += n * n
+        return perm, sizes, out
+
+    def transform(self, x) -> np.ndarray:
+        x = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+        z = np.empty(self.dim)
+        assert lib().orc_problem_transform(self._h, _dp(x), _dp(z)) == 0
+        return z
+
+
+def basic(fid: int, dim: int, seed: int) -> Problem:
+    """Tab. 1 function 0..22 with the transform its section states."""
+    return Problem(lib().orc_problem_basic(fid, dim, seed))
+
+
+def fid_problem(fid: int, dim: int, seed: int) -> Problem:
+    """Any Tab. 1 id 0..36 (hybrids and compositions use the paper's fixed tables)."""
+    return Problem(lib().orc_problem_fid(fid, dim, seed))
+
+
+def custom_basic(pid: int, base: int, dim: int, seed: int, scale: float, offset: float, rotated: bool) -> Problem:
+    return Problem(lib().orc_problem_custom_basic(pid, base, dim, seed, scale, offset, int(rotated)))
+
+
+def hybrid(pid: int, dim: int, seed: int, bases, p) -> Problem:
+    b = np.ascontiguousarray(bases, dtype=np.int32)
+    pp = np.ascontiguousarray(p, dtype=np.float64)
+    return Problem(lib().orc_problem_hybrid(pid, dim, seed, len(b), _ip(b), _dp(pp)))
+
+
+def composition(pid: int, dim: int, seed: int, bases, sigma, lam, bias) -> Problem:
+    b = np.ascontiguousarray(bases, dtype=np.int32)
+    s = np.ascontiguousarray(sigma, dtype=np.float64)
+    lm = np.ascontiguousarray(lam, dtype=np.float64)
+    bi = np.ascontiguousarray(bias, dtype=np.float64)
+    return Problem(lib().orc_problem_composition(pid, dim, seed, len(b), _ip(b), _dp(s), _dp(lm), _dp(bi)))
+
+
+def g(fid: int, z) -> float:
+    """Formula g(z) of Tab. 1 function 0..22 on a given z, without the bias."""
+    z = np.ascontiguousarray(np.asarray(z, dtype=np.float64))
+    return float(lib().orc_g(fid, z.shape[0], _dp(z)))
+
+
+def stream_u64(seed: int, dim: int, key: int, purpose: int, n: int) -> np.ndarray:
+    out = np.empty(n, dtype=np.uint64)
+    lib().orc_stream_u64(seed, dim, key, purpose, n, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)))
+    return out
+
+
+def stream_normal(seed: int, dim: int, key: int, purpose: int, n: int) -> np.ndarray:
+    out = np.empty(n)
+    lib().orc_stream_normal(seed, dim, key, purpose, n, _dp(out))
+    return out
+
+
+def splitmix64_from_state(state: int, k: int) -> int:
+    return int(lib().orc_splitmix64_from_state(state, k))
+
+
+def orthonormalise(A) -> np.ndarray:
+    A = np.ascontiguousarray(np.array(A, dtype=np.float64))
+    lib().orc_orthonormalise(A.shape[0], _dp(A))
+    return A
+
+
+def threads_available() -> int:
+    return int(lib().orc_num_threads_available())
