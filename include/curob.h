@@ -1,0 +1,153 @@
+/*
+ * curob.h -- C ABI of libcurob.so, an MI355X (gfx950) evaluator for the cuROB real-parameter
+ * test functions (Ding & Tan, "A CUDA-Based Real Parameter Optimization Benchmark",
+ * arXiv 1407.7737).
+ *
+ * Every function evaluates f(x) = f_opt + g(R (s (x - o)) + c) for whole populations of
+ * candidate vectors, where g is one of the formulas of Secs. 3-4 (Tab. 1 ids 0-22), o is the
+ * shifted optimum, R the three-block orthogonal rotation and s, c the scale and offset of that
+ * function's definition; hybrids (Sec. 5) and compositions (Sec. 6) combine such pieces.
+ *
+ * Conventions for every call below.
+ *  - Return value: CUROB_OK (0) or a negative CUROB_E_* code; nothing throws or aborts.
+ *    curob_last_error() describes the most recent failure of the calling process.
+ *  - Layout: a population is n row-major candidate vectors of `dim` contiguous elements
+ *    (no padding); results are n contiguous values, one per row.
+ *  - Device pointers: func_evaluate / func_evaluatef take pointers to GPU memory (Sec. 1.3,
+ *    "Interface") and run asynchronously on the stream set by curob_set_stream (default: the
+ *    null stream).  The h_ variants take host memory and return after the results are copied
+ *    back (Sec. 1.3: wrappers of the GPU calls for CPU code).
+ *  - Ownership: the caller owns x and out; the library owns all problem data it generates,
+ *    and dispose() frees it.  One library context per process; calls are not thread-safe.
+ *  - Sizes: 0 <= n <= max_concurrency (the capacity fixed at initialize, Sec. 1.3); n = 0 is
+ *    a no-op.  A null pointer with n > 0 is CUROB_E_ARG.
+ */
+#ifndef CUROB_H
+#define CUROB_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CUROB_OK 0
+#define CUROB_E_STATE (-1)    /* called before initialize / after dispose / double initialize */
+#define CUROB_E_ARG (-2)      /* bad dimension, count, pointer or parameter */
+#define CUROB_E_FID (-3)      /* function id not defined */
+#define CUROB_E_CAPACITY (-4) /* n > max_concurrency */
+#define CUROB_E_HIP (-5)      /* HIP runtime failure (no device, out of memory, launch error) */
+
+/* FP32 entry point arithmetic, chosen by curob_set_mode.  The rotation runs on the matrix
+ * cores in every mode; the modes differ in how FP32 operands are represented there. */
+#define CUROB_MODE_SPLIT 0        /* default: BF16 split products, x3 or x6 chosen per formula */
+#define CUROB_MODE_FP32 1         /* FP32 MFMA products (the plain FP32 path) */
+#define CUROB_MODE_SPLIT_BF16X3 2 /* y = hi + lo, Q = hi + lo: hi*hi + hi*lo + lo*hi, FP32 accumulate */
+#define CUROB_MODE_SPLIT_BF16X6 3 /* three-term splits of y and Q, the six products of order <= 2 */
+
+/* Tab. 1 function ids (the `fid` argument) */
+enum curob_fid {
+  SPHERE = 0, ELLIPSOID = 1, ELLIPTIC = 2, DISCUS = 3, CIGAR = 4, POWERS = 5, SHARPV = 6,
+  STEP = 7, WEIERSTRASS = 8, GRIEWANK = 9, RASTRIGIN_U = 10, RASTRIGIN = 11, SCHAFFERSF7 = 12,
+  GRIE_ROSEN = 13, ROSENBROCK = 14, SCHWEFEL_U = 15, SCHWEFEL = 16, KATSUURA = 17, LUNACEK = 18,
+  ACKLEY = 19, HAPPYCAT = 20, HGBAT = 21, SCHAFFERSF6 = 22,
+  HYBRID1 = 23, HYBRID2 = 24, HYBRID3 = 25, HYBRID4 = 26, HYBRID5 = 27, HYBRID6 = 28,
+  COMPOSITION1 = 29, COMPOSITION2 = 30, COMPOSITION3 = 31, COMPOSITION4 = 32,
+  COMPOSITION5 = 33, COMPOSITION6 = 34, COMPOSITION7 = 35, COMPOSITION8 = 36
+};
+
+/* Custom problems defined at run time take ids in [CUROB_CUSTOM_ID_MIN, CUROB_CUSTOM_ID_MAX]. */
+#define CUROB_CUSTOM_ID_MIN 64
+#define CUROB_CUSTOM_ID_MAX 1023
+
+/* ---- the paper's interface (Sec. 1.3) ------------------------------------------------- */
+
+/* Performs all set-up (Sec. 1.3 "Interface"): draws every function's optimum o uniformly in
+ * [-70,70]^dim and its rotation from three random, almost equal variable groups, each block
+ * an orthonormalised matrix of N(0,1) entries (Sec. 1.2), all from `seed`; uploads them to the
+ * current HIP device and reserves staging for max_concurrency rows.  dim >= 2 (Sec. 1.2);
+ * hybrid ids need dim >= 10.  Errors: CUROB_E_STATE if already initialised, CUROB_E_ARG for
+ * dim < 2 or max_concurrency < 1, CUROB_E_HIP if no device or memory is available. */
+int initialize(int dim, int max_concurrency, unsigned long long seed);
+
+/* Releases everything initialize and later calls allocated (Sec. 1.3).  Returns CUROB_E_STATE
+ * when nothing is initialised. */
+int dispose(void);
+
+/* FP64 evaluation of function `fid` on n device-resident rows d_x (n x dim doubles), writing n
+ * doubles to d_out (Sec. 1.3, func_evaluate).  Asynchronous on the library stream. */
+int func_evaluate(int fid, const double *d_x, int n, double *d_out);
+
+/* FP32 evaluation (Sec. 1.3, func_evaluatef): n x dim floats in, n floats out, device
+ * pointers, asynchronous.  The rotation arithmetic follows curob_set_mode; in the default
+ * CUROB_MODE_SPLIT the formulas whose FP32 value amplifies rounding of z (elliptic, discus,
+ * step, Weierstrass, Schaffer F7, Griewank-Rosenbrock, rotated Schwefel, Katsuura) use the
+ * six-product split, all others the three-product split. */
+int func_evaluatef(int fid, const float *d_x, int n, float *d_out);
+
+/* Host-pointer wrappers of the two calls above (Sec. 1.3): copy h_x to the device, evaluate,
+ * copy the results to h_out and wait for them. */
+int h_func_evaluate(int fid, const double *h_x, int n, double *h_out);
+int h_func_evaluatef(int fid, const float *h_x, int n, float *h_out);
+
+/* ---- extensions ----------------------------------------------------------------------- */
+
+/* Stream for subsequent device-pointer calls (a hipStream_t; NULL = null stream). */
+int curob_set_stream(void *hip_stream);
+
+/* Rotation arithmetic of func_evaluatef: one of the CUROB_MODE_* values above. */
+int curob_set_mode(int mode);
+
+/* A basic formula `base` (0..22) under a caller-chosen transform z = R(scale (x - o)) + offset
+ * (rotated != 0) or z = scale (x - o) + offset, with its own random o and R; registered as
+ * custom id `id` for the current dimension.  Used, e.g., for Rastrigin at scale 1. */
+int curob_define_basic(int id, int base, double scale, double offset, int rotated);
+
+/* Hybrid function (Sec. 5, Eq. (hybrid)): y = x - o is permuted by a random S and cut into
+ * ngroups consecutive groups of sizes n_i = ceil(p_i dim) (i < ngroups) and the remainder
+ * (Eq. (numbers)); group i contributes g_{base_i}(R_i (s_i z^i) + c_i) at dimension n_i, with
+ * its own dense random rotation R_i.  Every n_i must be >= 2; 1 <= ngroups <= 8. */
+int curob_define_hybrid(int id, int ngroups, const int *bases, const double *p);
+
+/* Composition function (Sec. 6, Eqs. (composition) and (weight)): ncomp (1..8) basic
+ * components, each with its own random optimum o^i and rotation, blended with weights
+ * w_i = exp(-d_i^2 / (2 dim sigma_i^2)) / d_i, d_i = |x - o^i|, normalised to sum to one
+ * (one-hot at x = o^i): F = sum_i omega_i (lambda_i G_i(x) + bias_i) + f_opt. */
+int curob_define_composition(int id, int ncomp, const int *bases, const double *sigma,
+                             const double *lambda, const double *bias);
+
+/* Message for the last failure of any call ("" if none). */
+const char *curob_last_error(void);
+
+/* Generated problem data, for checks: the shift o (dim doubles) and the dense rotation R
+ * (dim x dim doubles, row-major; the identity when the function is unrotated).  Either
+ * pointer may be NULL.  Works for ids 0..22 and custom basic ids. */
+int curob_get_problem(int fid, double *o, double *R);
+
+/* Host-only generator entry point (no device needed): the same o and R that initialize(dim,
+ * ..., seed) produces for basic function `fid` (0..22). */
+int curob_generate_basic(int fid, int dim, unsigned long long seed, double *o, double *R);
+
+/* ---- batched populations (one launch, replayed as a HIP graph) -------------------------- */
+
+typedef struct curob_batch curob_batch;
+
+/* Plans k populations evaluated by one persistent launch: population i has counts[i] rows of
+ * dims[i] (2..128) elements and function fids[i] (0..22), each with its own o and R drawn from
+ * (seed, i).  The plan, device tables and a captured HIP graph are owned by *out. */
+int curob_batch_create(int k, const int *fids, const int *dims, const int *counts,
+                       unsigned long long seed, curob_batch **out);
+
+/* Points the batch at device buffers: d_xs[i] holds counts[i] x dims[i] floats, d_outs[i]
+ * receives counts[i] floats.  Arrays of k host-side entries. */
+int curob_batch_bind(curob_batch *b, const float *const *d_xs, float *const *d_outs);
+
+/* Replays the captured graph on the library stream (asynchronous). */
+int curob_batch_run(curob_batch *b);
+
+/* Frees a batch.  NULL is ignored. */
+int curob_batch_destroy(curob_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CUROB_H */

@@ -524,8 +524,12 @@ static orc_problem *orc_hybrid_keyed(int dim, uint64_t seed, uint32_t key, int n
     used += sizes[i];
   }
   sizes[ng - 1] = dim - used;
-  for (int i = 0; i < ng; ++i)
-    if (sizes[i] < 2 || bases[i] < 0 || bases[i] > 22) return NULL;
+  /* a group needs one variable, two for the formulas that divide by (n - 1): the elliptic and
+     different-powers exponents (i-1)/(n-1) and Schaffer's F7 mean over n-1 pairs */
+  for (int i = 0; i < ng; ++i) {
+    if (bases[i] < 0 || bases[i] > 22 || sizes[i] < 1) return NULL;
+    if (sizes[i] < 2 && (bases[i] == 2 || bases[i] == 5 || bases[i] == 12)) return NULL;
+  }
   orc_problem *h = orc_alloc(ORC_HYBRID, dim);
   h->ngroups = ng;
   h->o = (double *)malloc(sizeof(double) * (size_t)dim);

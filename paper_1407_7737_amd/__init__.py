@@ -1,0 +1,191 @@
+"""MI355X-native evaluator for the cuROB test functions (arXiv 1407.7737).
+
+Thin Python binding over libcurob.so with the names of the paper's interface (Sec. 1.3):
+``initialize``, ``dispose``, ``func_evaluate`` (FP64), ``func_evaluatef`` (FP32), the host
+wrappers ``h_func_evaluate`` / ``h_func_evaluatef``, plus the library extensions.  Torch
+tensors provide device memory and the stream; all evaluation happens in the HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _native
+from ._native import (CUROB_E_ARG, CUROB_E_CAPACITY, CUROB_E_FID, CUROB_E_HIP, CUROB_E_STATE, CUROB_OK,
+                      CUSTOM_ID_MAX, CUSTOM_ID_MIN, MODE_FP32, MODE_SPLIT, MODE_SPLIT_BF16X3,
+                      MODE_SPLIT_BF16X6, CurobError, check, last_error)
+
+lib = _native.lib
+
+# Tab. 1 ids
+SPHERE, ELLIPSOID, ELLIPTIC, DISCUS, CIGAR, POWERS, SHARPV = range(7)
+STEP, WEIERSTRASS, GRIEWANK, RASTRIGIN_U, RASTRIGIN, SCHAFFERSF7 = range(7, 13)
+GRIE_ROSEN, ROSENBROCK, SCHWEFEL_U, SCHWEFEL, KATSUURA, LUNACEK = range(13, 19)
+ACKLEY, HAPPYCAT, HGBAT, SCHAFFERSF6 = range(19, 23)
+HYBRID1, COMPOSITION1 = 23, 29
+
+__all__ = [
+    "initialize", "dispose", "func_evaluate", "func_evaluatef", "h_func_evaluate", "h_func_evaluatef",
+    "set_stream", "set_mode", "define_basic", "define_hybrid", "define_composition", "get_problem",
+    "generate_basic", "last_error", "CurobError", "Batch",
+]
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _torch_stream():
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def initialize(dim: int, max_concurrency: int, seed: int = 0) -> None:
+    check(lib.initialize(int(dim), int(max_concurrency), int(seed)))
+
+
+def dispose() -> None:
+    check(lib.dispose())
+
+
+def set_stream(stream=None) -> None:
+    """Stream for device-pointer calls: a torch.cuda.Stream, a raw hipStream_t or None."""
+    if stream is None:
+        h = None
+    elif isinstance(stream, int):
+        h = stream
+    else:
+        h = stream.cuda_stream
+    check(lib.curob_set_stream(h))
+
+
+def set_mode(mode: int) -> None:
+    check(lib.curob_set_mode(int(mode)))
+
+
+def _eval_device(fn, fid, x, out, dtype_name):
+    import torch
+    want = torch.float64 if dtype_name == "f64" else torch.float32
+    if not (x.is_cuda and x.dtype == want and x.is_contiguous() and x.dim() == 2):
+        raise ValueError(f"x must be a contiguous 2-D {want} CUDA tensor")
+    n = x.shape[0]
+    if out is None:
+        out = torch.empty(n, dtype=want, device=x.device)
+    elif not (out.is_cuda and out.dtype == want and out.is_contiguous() and out.numel() >= n):
+        raise ValueError(f"out must be a contiguous {want} CUDA tensor with at least {n} entries")
+    check(lib.curob_set_stream(_torch_stream()))
+    check(fn(int(fid), _ptr(x), int(n), _ptr(out)))
+    return out
+
+
+def func_evaluate(fid: int, x, out=None):
+    """FP64 evaluation of n x dim device rows; returns the (n,) device result."""
+    return _eval_device(lib.func_evaluate, fid, x, out, "f64")
+
+
+def func_evaluatef(fid: int, x, out=None):
+    """FP32 evaluation (BF16 split rotation by default, see set_mode)."""
+    return _eval_device(lib.func_evaluatef, fid, x, out, "f32")
+
+
+def func_evaluate_ptr(fid: int, d_x: int, n: int, d_out: int) -> None:
+    """Raw device-pointer form of func_evaluate (no checks beyond the library's own)."""
+    check(lib.func_evaluate(int(fid), d_x, int(n), d_out))
+
+
+def func_evaluatef_ptr(fid: int, d_x: int, n: int, d_out: int) -> None:
+    check(lib.func_evaluatef(int(fid), d_x, int(n), d_out))
+
+
+def _eval_host(fn, fid, x, dt):
+    x = np.ascontiguousarray(np.asarray(x, dtype=dt))
+    if x.ndim == 1:
+        x = x[None, :]
+    out = np.empty(x.shape[0], dtype=dt)
+    check(fn(int(fid), x.ctypes.data, int(x.shape[0]), out.ctypes.data))
+    return out
+
+
+def h_func_evaluate(fid: int, x) -> np.ndarray:
+    """Host-pointer FP64 evaluation (copies in, evaluates, copies out, waits)."""
+    return _eval_host(lib.h_func_evaluate, fid, x, np.float64)
+
+
+def h_func_evaluatef(fid: int, x) -> np.ndarray:
+    return _eval_host(lib.h_func_evaluatef, fid, x, np.float32)
+
+
+def define_basic(pid: int, base: int, scale: float, offset: float = 0.0, rotated: bool = True) -> None:
+    check(lib.curob_define_basic(int(pid), int(base), float(scale), float(offset), int(bool(rotated))))
+
+
+def define_hybrid(pid: int, bases, p) -> None:
+    b = np.ascontiguousarray(bases, dtype=np.int32)
+    pp = np.ascontiguousarray(p, dtype=np.float64)
+    check(lib.curob_define_hybrid(int(pid), len(b), b.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                  pp.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+
+
+def define_composition(pid: int, bases, sigma, lam, bias) -> None:
+    b = np.ascontiguousarray(bases, dtype=np.int32)
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (sigma, lam, bias)]
+    dp = ctypes.POINTER(ctypes.c_double)
+    check(lib.curob_define_composition(int(pid), len(b), b.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                       *[a.ctypes.data_as(dp) for a in arrs]))
+
+
+def get_problem(fid: int, dim: int):
+    o = np.empty(dim)
+    R = np.empty((dim, dim))
+    dp = ctypes.POINTER(ctypes.c_double)
+    check(lib.curob_get_problem(int(fid), o.ctypes.data_as(dp), R.ctypes.data_as(dp)))
+    return o, R
+
+
+def generate_basic(fid: int, dim: int, seed: int):
+    """Host-only: the shift and dense rotation initialize(dim, ..., seed) draws for fid."""
+    o = np.empty(dim)
+    R = np.empty((dim, dim))
+    dp = ctypes.POINTER(ctypes.c_double)
+    check(lib.curob_generate_basic(int(fid), int(dim), int(seed), o.ctypes.data_as(dp), R.ctypes.data_as(dp)))
+    return o, R
+
+
+class Batch:
+    """Populations of uneven size, dimension and function evaluated by one persistent launch
+    replayed as a HIP graph (curob_batch_*)."""
+
+    def __init__(self, fids, dims, counts, seed: int = 0):
+        self.k = len(fids)
+        arr = [np.ascontiguousarray(a, dtype=np.int32) for a in (fids, dims, counts)]
+        ip = ctypes.POINTER(ctypes.c_int)
+        h = ctypes.c_void_p()
+        check(lib.curob_batch_create(self.k, *[a.ctypes.data_as(ip) for a in arr], int(seed), ctypes.byref(h)))
+        self._h = h
+        self.fids, self.dims, self.counts = (a.copy() for a in arr)
+
+    def bind(self, xs, outs) -> None:
+        X = (ctypes.c_void_p * self.k)(*[_ptr(t) for t in xs])
+        O = (ctypes.c_void_p * self.k)(*[_ptr(t) for t in outs])
+        self._keep = (xs, outs)
+        check(lib.curob_batch_bind(self._h, X, O))
+
+    def run(self) -> None:
+        check(lib.curob_set_stream(_torch_stream()))
+        check(lib.curob_batch_run(self._h))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib.curob_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

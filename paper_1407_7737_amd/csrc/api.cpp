@@ -1,0 +1,325 @@
+// api.cpp -- the C ABI of include/curob.h: state machine, validation, problem registry,
+// dispatch to the evaluation kernels and the host-pointer wrappers (Sec. 1.3).
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+
+#include "../../include/curob.h"
+#include "batch.h"
+#include "composite.h"
+#include "kernels.h"
+#include "problem.h"
+#include "tables.h"
+
+namespace curob {
+namespace {
+
+struct Entry {
+  Problem host;
+  DevTables dev[PATH_COUNT];
+  CompositeDev comp;  // hybrids and compositions
+  ~Entry() {
+    for (auto &d : dev) d.release();
+    comp.release();
+  }
+};
+
+struct Context {
+  bool ready = false;
+  int dim = 0;
+  int maxc = 0;
+  uint64_t seed = 0;
+  int device = 0;
+  int num_cu = 0;
+  int mode = CUROB_MODE_SPLIT;
+  hipStream_t stream = nullptr;
+  std::map<int, std::unique_ptr<Entry>> entries;
+  void *stage_x = nullptr;    // maxc * dim doubles, for the h_ wrappers
+  void *stage_out = nullptr;  // maxc doubles
+};
+
+Context g_ctx;
+std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+  return fail(CUROB_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+void free_context() {
+  g_ctx.entries.clear();
+  if (g_ctx.stage_x) (void)hipFree(g_ctx.stage_x);
+  if (g_ctx.stage_out) (void)hipFree(g_ctx.stage_out);
+  g_ctx = Context{};
+}
+
+// Builds device data for a problem on every path; basic problems get the resident tables,
+// hybrids and compositions the segmented / composite tables.
+int prepare_entry(Entry &e) {
+  const Problem &p = e.host;
+  if (p.type == Problem::BASIC) {
+    for (int path = 0; path < PATH_COUNT; ++path) {
+      if (p.dim <= 16 * kMaxMT) {
+        HostTables ht;
+        std::string err;
+        if (!build_host_tables(p, path, ht, err)) return fail(CUROB_E_ARG, "%s", err.c_str());
+        hipError_t he = upload_tables(ht, e.dev[path]);
+        if (he != hipSuccess) return hip_fail(he, "uploading problem tables");
+      }
+    }
+  }
+  hipError_t he = build_composite(p, e.comp);
+  if (he != hipSuccess) return hip_fail(he, "uploading composite tables");
+  return CUROB_OK;
+}
+
+int register_problem(int id, Problem &&p) {
+  auto e = std::make_unique<Entry>();
+  e->host = std::move(p);
+  int rc = prepare_entry(*e);
+  if (rc != CUROB_OK) return rc;
+  g_ctx.entries[id] = std::move(e);
+  return CUROB_OK;
+}
+
+// FP32 entry point: the arithmetic path for a problem under the current mode.
+int fp32_path(int fid) {
+  switch (g_ctx.mode) {
+    case CUROB_MODE_FP32: return PATH_F32;
+    case CUROB_MODE_SPLIT_BF16X3: return PATH_SPLIT;
+    case CUROB_MODE_SPLIT_BF16X6: return PATH_SPLIT6;
+    default: break;
+  }
+  auto it = g_ctx.entries.find(fid);
+  if (it == g_ctx.entries.end() || it->second->host.segs.empty()) return PATH_SPLIT;
+  return needs_six_products(it->second->host.segs[0].base) ? PATH_SPLIT6 : PATH_SPLIT;
+}
+
+int check_ready() {
+  if (!g_ctx.ready) return fail(CUROB_E_STATE, "library is not initialised (call initialize first)");
+  return CUROB_OK;
+}
+
+int check_eval_args(int fid, const void *x, int n, const void *out, Entry **entry) {
+  int rc = check_ready();
+  if (rc != CUROB_OK) return rc;
+  auto it = g_ctx.entries.find(fid);
+  if (it == g_ctx.entries.end()) return fail(CUROB_E_FID, "function id %d is not defined for dim %d", fid, g_ctx.dim);
+  if (n < 0) return fail(CUROB_E_ARG, "n must be >= 0 (got %d)", n);
+  if (n > g_ctx.maxc) return fail(CUROB_E_CAPACITY, "n = %d exceeds max_concurrency %d", n, g_ctx.maxc);
+  if (n > 0 && (x == nullptr || out == nullptr)) return fail(CUROB_E_ARG, "null pointer with n > 0");
+  *entry = it->second.get();
+  return CUROB_OK;
+}
+
+int evaluate(int path, int fid, const void *x, int n, void *out) {
+  Entry *e = nullptr;
+  int rc = check_eval_args(fid, x, n, out, &e);
+  if (rc != CUROB_OK || n == 0) return rc;
+  hipError_t he;
+  if (e->host.type == Problem::BASIC && e->dev[path].ready) {
+    const DevProb &pb = e->dev[path].pb;
+    const int grid = resident_grid(path, pb, n, g_ctx.num_cu);
+    he = launch_resident(path, pb, x, out, n, grid, g_ctx.stream);
+  } else {
+    he = launch_composite(path, e->comp, x, out, n, g_ctx.num_cu, g_ctx.stream);
+  }
+  if (he != hipSuccess) return hip_fail(he, "kernel launch");
+  return CUROB_OK;
+}
+
+template <typename T>
+int h_evaluate(int path, int fid, const T *hx, int n, T *hout) {
+  Entry *e = nullptr;
+  int rc = check_eval_args(fid, hx, n, hout, &e);
+  if (rc != CUROB_OK || n == 0) return rc;
+  const size_t xb = static_cast<size_t>(n) * g_ctx.dim * sizeof(T);
+  hipError_t he = hipMemcpyAsync(g_ctx.stage_x, hx, xb, hipMemcpyHostToDevice, g_ctx.stream);
+  if (he != hipSuccess) return hip_fail(he, "copying inputs to the device");
+  rc = evaluate(path, fid, g_ctx.stage_x, n, g_ctx.stage_out);
+  if (rc != CUROB_OK) return rc;
+  he = hipMemcpyAsync(hout, g_ctx.stage_out, static_cast<size_t>(n) * sizeof(T), hipMemcpyDeviceToHost, g_ctx.stream);
+  if (he != hipSuccess) return hip_fail(he, "copying results to the host");
+  he = hipStreamSynchronize(g_ctx.stream);
+  if (he != hipSuccess) return hip_fail(he, "waiting for the evaluation");
+  return CUROB_OK;
+}
+
+}  // namespace
+
+int context_num_cu() { return g_ctx.num_cu; }
+hipStream_t context_stream() { return g_ctx.stream; }
+int set_error(int code, const std::string &msg) { return fail(code, "%s", msg.c_str()); }
+
+}  // namespace curob
+
+using namespace curob;
+
+extern "C" {
+
+int initialize(int dim, int max_concurrency, unsigned long long seed) {
+  if (g_ctx.ready) return fail(CUROB_E_STATE, "already initialised (call dispose first)");
+  if (dim < 2) return fail(CUROB_E_ARG, "dim must be >= 2 (got %d)", dim);
+  if (max_concurrency < 1) return fail(CUROB_E_ARG, "max_concurrency must be >= 1 (got %d)", max_concurrency);
+  int ndev = 0;
+  hipError_t he = hipGetDeviceCount(&ndev);
+  if (he != hipSuccess || ndev < 1) return fail(CUROB_E_HIP, "no HIP device available");
+  he = hipGetDevice(&g_ctx.device);
+  if (he != hipSuccess) return hip_fail(he, "hipGetDevice");
+  hipDeviceProp_t prop;
+  he = hipGetDeviceProperties(&prop, g_ctx.device);
+  if (he != hipSuccess) return hip_fail(he, "hipGetDeviceProperties");
+  g_ctx.num_cu = prop.multiProcessorCount;
+  g_ctx.dim = dim;
+  g_ctx.maxc = max_concurrency;
+  g_ctx.seed = seed;
+  try {
+    for (int fid = 0; fid <= 36; ++fid) {
+      if (fid >= 23 && fid <= 28 && dim < 10) continue;  // hybrids need dim >= 10 (Sec. 1.2)
+      if ((fid == 35 || fid == 36) && dim < 10) continue;
+      int rc = register_problem(fid, make_tab1(fid, dim, seed));
+      if (rc != CUROB_OK) {
+        free_context();
+        return rc;
+      }
+    }
+  } catch (const std::exception &ex) {
+    free_context();
+    return fail(CUROB_E_ARG, "%s", ex.what());
+  }
+  const size_t xb = static_cast<size_t>(max_concurrency) * dim * sizeof(double);
+  he = hipMalloc(&g_ctx.stage_x, xb);
+  if (he == hipSuccess) he = hipMalloc(&g_ctx.stage_out, static_cast<size_t>(max_concurrency) * sizeof(double));
+  if (he != hipSuccess) {
+    free_context();
+    return hip_fail(he, "allocating staging buffers");
+  }
+  g_ctx.ready = true;
+  g_err.clear();
+  return CUROB_OK;
+}
+
+int dispose(void) {
+  if (!g_ctx.ready) return fail(CUROB_E_STATE, "nothing to dispose");
+  (void)hipStreamSynchronize(g_ctx.stream);
+  free_context();
+  return CUROB_OK;
+}
+
+int func_evaluate(int fid, const double *d_x, int n, double *d_out) { return evaluate(PATH_F64, fid, d_x, n, d_out); }
+
+int func_evaluatef(int fid, const float *d_x, int n, float *d_out) { return evaluate(fp32_path(fid), fid, d_x, n, d_out); }
+
+int h_func_evaluate(int fid, const double *h_x, int n, double *h_out) {
+  return h_evaluate<double>(PATH_F64, fid, h_x, n, h_out);
+}
+
+int h_func_evaluatef(int fid, const float *h_x, int n, float *h_out) {
+  return h_evaluate<float>(fp32_path(fid), fid, h_x, n, h_out);
+}
+
+int curob_set_stream(void *hip_stream) {
+  int rc = check_ready();
+  if (rc != CUROB_OK) return rc;
+  g_ctx.stream = static_cast<hipStream_t>(hip_stream);
+  return CUROB_OK;
+}
+
+int curob_set_mode(int mode) {
+  int rc = check_ready();
+  if (rc != CUROB_OK) return rc;
+  if (mode < CUROB_MODE_SPLIT || mode > CUROB_MODE_SPLIT_BF16X6) return fail(CUROB_E_ARG, "unknown mode %d", mode);
+  g_ctx.mode = mode;
+  return CUROB_OK;
+}
+
+static int check_custom_id(int id) {
+  if (id < CUROB_CUSTOM_ID_MIN || id > CUROB_CUSTOM_ID_MAX)
+    return fail(CUROB_E_ARG, "custom ids must be in [%d, %d]", CUROB_CUSTOM_ID_MIN, CUROB_CUSTOM_ID_MAX);
+  return CUROB_OK;
+}
+
+int curob_define_basic(int id, int base, double scale, double offset, int rotated) {
+  int rc = check_ready();
+  if (rc == CUROB_OK) rc = check_custom_id(id);
+  if (rc != CUROB_OK) return rc;
+  if (base < 0 || base > 22) return fail(CUROB_E_ARG, "base must be in 0..22");
+  try {
+    return register_problem(id, make_basic(base, g_ctx.dim, g_ctx.seed, static_cast<uint32_t>(id) << 8, scale, offset,
+                                           rotated != 0, false));
+  } catch (const std::exception &ex) {
+    return fail(CUROB_E_ARG, "%s", ex.what());
+  }
+}
+
+int curob_define_hybrid(int id, int ngroups, const int *bases, const double *p) {
+  int rc = check_ready();
+  if (rc == CUROB_OK) rc = check_custom_id(id);
+  if (rc != CUROB_OK) return rc;
+  if (!bases || !p) return fail(CUROB_E_ARG, "null pointer");
+  try {
+    return register_problem(id, make_hybrid(g_ctx.dim, g_ctx.seed, static_cast<uint32_t>(id) << 8, ngroups, bases, p));
+  } catch (const std::exception &ex) {
+    return fail(CUROB_E_ARG, "%s", ex.what());
+  }
+}
+
+int curob_define_composition(int id, int ncomp, const int *bases, const double *sigma, const double *lambda,
+                             const double *bias) {
+  int rc = check_ready();
+  if (rc == CUROB_OK) rc = check_custom_id(id);
+  if (rc != CUROB_OK) return rc;
+  if (!bases || !sigma || !lambda || !bias) return fail(CUROB_E_ARG, "null pointer");
+  try {
+    return register_problem(
+        id, make_composition(g_ctx.dim, g_ctx.seed, static_cast<uint32_t>(id) << 8, ncomp, bases, sigma, lambda, bias));
+  } catch (const std::exception &ex) {
+    return fail(CUROB_E_ARG, "%s", ex.what());
+  }
+}
+
+const char *curob_last_error(void) { return g_err.c_str(); }
+
+int curob_get_problem(int fid, double *o, double *R) {
+  int rc = check_ready();
+  if (rc != CUROB_OK) return rc;
+  auto it = g_ctx.entries.find(fid);
+  if (it == g_ctx.entries.end()) return fail(CUROB_E_FID, "function id %d is not defined", fid);
+  const Problem &p = it->second->host;
+  if (p.type != Problem::BASIC) return fail(CUROB_E_FID, "id %d is not a basic function", fid);
+  if (o) std::memcpy(o, p.o.data(), sizeof(double) * p.dim);
+  if (R) {
+    std::vector<double> d = dense_rotation(p);
+    std::memcpy(R, d.data(), sizeof(double) * d.size());
+  }
+  return CUROB_OK;
+}
+
+int curob_generate_basic(int fid, int dim, unsigned long long seed, double *o, double *R) {
+  if (fid < 0 || fid > 22) return fail(CUROB_E_FID, "fid must be in 0..22");
+  if (dim < 2) return fail(CUROB_E_ARG, "dim must be >= 2");
+  Problem p = make_tab1_basic(fid, dim, seed);
+  if (o) std::memcpy(o, p.o.data(), sizeof(double) * dim);
+  if (R) {
+    std::vector<double> d = dense_rotation(p);
+    std::memcpy(R, d.data(), sizeof(double) * d.size());
+  }
+  return CUROB_OK;
+}
+
+}  // extern "C"

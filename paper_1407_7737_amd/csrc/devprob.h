@@ -1,0 +1,54 @@
+// devprob.h -- the per-problem device tables handed to the evaluation kernels by value.
+// Shared by the host table builder and the kernels; plain data only.
+#pragma once
+
+#include <cstdint>
+
+namespace curob {
+
+// Arithmetic of one evaluation path.
+enum Path : int {
+  PATH_SPLIT = 0,   // FP32 data, rotation as three BF16 MFMA products (hi*hi + hi*lo + lo*hi)
+  PATH_F32 = 1,     // FP32 data, rotation on FP32 MFMA
+  PATH_F64 = 2,     // FP64 data, rotation on FP64 MFMA
+  PATH_SPLIT6 = 3,  // FP32 data, three-term BF16 splits of y and Q, six MFMA products
+  PATH_COUNT = 4
+};
+
+inline constexpr bool is_split(int path) { return path == PATH_SPLIT || path == PATH_SPLIT6; }
+// bf16 fragments stored per rotation tile: hi, lo (x3) or hi, mid, lo (x6)
+inline constexpr int split_terms(int path) { return path == PATH_SPLIT6 ? 3 : 2; }
+
+// Tile geometry of the block-diagonal rotation in packed (group-ordered) variable space.
+// The MFMA computes Z^T = Qp * Y^T tile by tile: Qp is the packed block-diagonal matrix,
+// m-tiles are 16 output positions, k-tiles are KW input positions (32 for BF16, 4 for FP32/64).
+constexpr int kMaxMT = 8;         // m-tiles supported by the resident kernel (dimension <= 128)
+constexpr int kRowsPerWave = 16;  // population rows per wave iteration (the MFMA N dimension)
+constexpr int kWavesPerWG = 4;
+
+inline constexpr int kw_of(int path) { return is_split(path) ? 32 : 4; }
+
+struct DevProb {
+  // every pointer is device memory owned by the library
+  const void *o;          // shift, original order, D entries (float or double per path)
+  const void *olo;        // FP32 paths: o - float(o), so (x - o_hi) - o_lo keeps y accurate near o
+  const void *sj;         // scale s per original variable, D entries
+  const uint16_t *orig;   // packed position -> original variable; KT*KW entries, padding -> D
+  const void *coef;       // per packed position coefficient, 16*MT entries
+  const void *cz;         // per packed position post-offset c, 16*MT entries
+  const int16_t *succ;    // per packed position: packed position of the formula successor or -1
+  const void *qfrag;      // nonzero rotation tiles in MFMA operand order (path-specific layout)
+  const int *ktab;        // per k-tile: first m-tile, last m-tile, first tile index, 0
+  int D;                  // dimension
+  int S;                  // LDS row stride in elements (>= D+1, 4*odd)
+  int KT;                 // k-tiles
+  int MT;                 // m-tiles
+  int ntiles;             // nonzero tiles
+  int rotated;            // 0: z = y + c directly
+  int kind;               // formula family (problem.h Kind)
+  int Df;                 // dimension seen by the formula
+  double bias;            // f_opt
+  double kparam;          // family parameter (Katsuura exponent 10/D^1.2)
+};
+
+}  // namespace curob

@@ -1,0 +1,62 @@
+// kernels.h -- launch entry points of the evaluation kernels and the LDS layout they share
+// with the host-side table builder.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+#include "devprob.h"
+
+namespace curob {
+
+struct LdsLayout {
+  int q, o, olo, s, orig, coef, cz, succ, y;  // byte offsets
+  int q_bytes, vec_bytes, orig_bytes, mp_bytes, succ_bytes, y_bytes;
+  int total;
+};
+
+__host__ __device__ inline int round16(int b) { return (b + 15) & ~15; }
+
+// LDS carve of the resident kernel: rotation tiles, per-variable tables, per-position tables,
+// then one 16 x S slice per wave for the staged rows.
+__host__ __device__ inline LdsLayout lds_layout(int path, const DevProb &pb) {
+  const int esz = path == PATH_F64 ? 8 : 4;
+  const int kw = kw_of(path);
+  LdsLayout L;
+  L.q_bytes = pb.rotated ? round16(pb.ntiles * 64 * (is_split(path) ? 16 * split_terms(path) : esz)) : 0;
+  L.orig_bytes = pb.rotated ? round16(pb.KT * kw * 2) : 0;
+  L.vec_bytes = round16(pb.D * esz);
+  L.mp_bytes = round16(16 * pb.MT * esz);
+  L.succ_bytes = round16(16 * pb.MT * 2);
+  L.y_bytes = kWavesPerWG * kRowsPerWave * pb.S * esz;
+  int off = 0;
+  L.q = off;
+  off += L.q_bytes;
+  L.orig = off;
+  off += L.orig_bytes;
+  L.o = off;
+  off += L.vec_bytes;
+  L.olo = off;
+  off += path == PATH_F64 ? 0 : L.vec_bytes;
+  L.s = off;
+  off += L.vec_bytes;
+  L.coef = off;
+  off += L.mp_bytes;
+  L.cz = off;
+  off += L.mp_bytes;
+  L.succ = off;
+  off += L.succ_bytes;
+  L.y = off;
+  off += round16(L.y_bytes);
+  L.total = off;
+  return L;
+}
+
+// Resident kernel (dimension <= 128): evaluates n rows of x (device, row-major) into out.
+hipError_t launch_resident(int path, const DevProb &pb, const void *x, void *out, int n, int grid, hipStream_t st);
+
+// Occupancy-derived workgroup count for the resident kernel.
+int resident_grid(int path, const DevProb &pb, int n, int num_cu);
+
+}  // namespace curob

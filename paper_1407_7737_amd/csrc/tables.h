@@ -1,0 +1,46 @@
+// tables.h -- host construction of the device tables for one problem and one path.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "devprob.h"
+#include "problem.h"
+
+namespace curob {
+
+// Device memory owned by one problem for one path.
+struct DevTables {
+  std::vector<void *> allocs;
+  DevProb pb{};
+  bool ready = false;
+  void release();
+};
+
+// Host-side images of the tables (exposed for CPU checks of the layout).
+struct HostTables {
+  int path = 0;
+  std::vector<unsigned char> o, olo, sj, coef, cz, qfrag;
+  std::vector<uint16_t> orig;
+  std::vector<int16_t> succ;
+  std::vector<int> ktab;
+  DevProb pb{};
+};
+
+// Builds the images for a basic problem of dimension <= 128 (the resident kernel's range).
+// Returns false with a message when the problem is outside that range.
+bool build_host_tables(const Problem &p, int path, HostTables &ht, std::string &err);
+
+// Uploads the images; pb pointers then refer to device memory.
+hipError_t upload_tables(const HostTables &ht, DevTables &dt);
+
+// Round-to-nearest-even float -> bf16 bits, as the device conversion does.
+uint16_t bf16_bits_rne(float f);
+float bf16_bits_to_float(uint16_t h);
+
+// LDS row stride: the smallest 4u >= D + 1 with u odd (16 rows then fall in distinct banks).
+int lds_stride(int D);
+
+}  // namespace curob

@@ -22,9 +22,17 @@ def test_hybrid_group_sizes_follow_the_ceiling_rule(orc):
             assert np.abs(B.T @ B - np.eye(B.shape[0])).max() <= 1e-13
 
 
-def test_hybrid_rejects_groups_below_two(orc):
+def test_hybrid_group_size_rules(orc):
+    # an elliptic group of one variable has the exponent 0/0: rejected
     with pytest.raises(ValueError):
         orc.hybrid(201, 10, 0, [2, 2, 2], [0.05, 0.9, 0.05])
+    # Schaffer F6 and Katsuura are defined on one variable (Hybrid 5 and 6 at D = 10)
+    h = orc.hybrid(201, 10, 0, [22, 17, 2], [0.1, 0.1, 0.8])
+    assert h.hybrid_parts()[1].tolist() == [1, 1, 8]
+    assert abs(h(h.shift())[0] - 100.0) < 1e-12
+    for fid in (27, 28):
+        p = orc.fid_problem(fid, 10, 0)
+        assert p(p.shift())[0] >= 100.0
 
 
 def test_hybrid_of_spheres_is_the_shifted_sphere(orc):
