@@ -134,8 +134,7 @@ int evaluate(int path, int fid, const void *x, int n, void *out) {
   hipError_t he;
   if (e->host.type == Problem::BASIC && e->dev[path].ready) {
     const DevProb &pb = e->dev[path].pb;
-    const int grid = resident_grid(path, pb, n, g_ctx.num_cu);
-    he = launch_resident(path, pb, x, out, n, grid, g_ctx.stream);
+    he = launch_resident(path, pb, x, out, n, resident_shape(path, pb, n, g_ctx.num_cu), g_ctx.stream);
   } else {
     he = launch_composite(path, e->comp, x, out, n, g_ctx.num_cu, g_ctx.stream);
   }

@@ -1,19 +1,20 @@
-// eval_resident.hip -- fused evaluation kernel for basic functions of dimension <= 128.
+// eval_resident.h -- fused evaluation kernel for basic functions of dimension <= 128.
 //
-// One wave evaluates 16 candidate rows at a time:
-//   1. stage   the 16 x D block of x (contiguous in HBM) with 16-byte loads, form
-//              y = s (x - o) and store it row-major in the wave's LDS slice;
-//   2. rotate  Z^T = Qp Y^T on the matrix cores, tile by tile over the nonzero tiles of the
-//              packed block-diagonal rotation (Sec. 1.2: three random variable groups, one
-//              orthonormal block each).  The B operand is gathered from LDS in group order;
-//              for the split path each y is split into bf16 hi + lo and three products
-//              hi*hi + hi*lo + lo*hi accumulate in FP32;
-//   3. phi     add the offset c and apply the formula to the lane's accumulator fragment
+// Each wave evaluates 16 candidate rows at a time and loops over row groups (grid-stride):
+//   1. stage   the 16 x D block of x (contiguous in HBM) was loaded into registers during the
+//              previous iteration; form y = s (x - o) and store it row-major in the wave's LDS
+//              slice, then immediately issue the loads of the wave's next row group so that
+//              HBM traffic overlaps everything below;
+//   2. rotate  Z^T = Qp Y^T on the matrix cores over the nonzero tiles of the packed
+//              block-diagonal rotation (Sec. 1.2: three random variable groups, one orthonormal
+//              block each).  The B operand is gathered from LDS in group order; on the split
+//              paths each y is cut into bf16 terms and the products accumulate in FP32;
+//   3. phi     add the offset c and apply the formula straight from the accumulator fragment
 //              (pairwise families first exchange z through LDS to reach z_{i+1});
-//   4. reduce  per-lane compensated sums, then a two-step cross-lane combine, finalise the
-//              formula and write one value per row.
-// The rotation tiles and per-position tables sit in LDS once per workgroup; each wave then
-// loops over row groups (grid-stride) without further workgroup barriers.
+//   4. reduce  per-lane compensated sums, a two-step cross-lane combine, finalise, store.
+// The rotation tiles and per-position tables sit in LDS once per workgroup.
+#pragma once
+
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -30,18 +31,9 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 template <int P>
-struct PathT;
-template <>
-struct PathT<PATH_SPLIT> {
+struct PathT {
   using T = float;
-  using V = f32x4;   // 16-byte staging vector
-  using Acc4 = f32x4;
-  static constexpr int KW = 32;
-};
-template <>
-struct PathT<PATH_SPLIT6> {
-  using T = float;
-  using V = f32x4;
+  using V = f32x4;  // 16-byte staging vector
   using Acc4 = f32x4;
   static constexpr int KW = 32;
 };
@@ -81,38 +73,39 @@ __device__ __forceinline__ void copy_to_lds(unsigned char *dst, const void *src,
   for (int i = threadIdx.x; i < (bytes >> 4); i += blockDim.x) d[i] = s[i];
 }
 
-// Stage rows [row0, row0 + nrows) of x into Y (row stride S): Y[r][j] = s_j (x[r][j] - o_j).
-// FP32 paths subtract o as a hi + lo pair: x - o_hi is exact near the optimum, so y keeps
-// its relative accuracy where the formula weights (up to 1e6) would amplify an absolute error.
+// Registers holding one wave's 16 x D slice of x between its load and its staging.
 template <int P>
-__device__ __forceinline__ void stage(const typename PathT<P>::T *__restrict__ xg, int tot, int D, int S, bool vec,
-                                      typename PathT<P>::T *Y, const typename PathT<P>::T *so,
-                                      const typename PathT<P>::T *sol, const typename PathT<P>::T *ss, int lane) {
+struct XTile {
   using T = typename PathT<P>::T;
   using V = typename PathT<P>::V;
-  constexpr int NV = 16 / sizeof(T);
-  if (vec) {
-    // 16 rows x at most 128 elements, NV elements per load
-    constexpr int TMAX = (kRowsPerWave * 128) / (64 * NV);
-    V v[TMAX];
+  static constexpr int NV = 16 / sizeof(T);
+  static constexpr int TMAX = (kRowsPerWave * 16 * kMaxMT) / (64 * NV);
+  V v[TMAX];
+
+  // 16-byte loads of elements (lane + 64 t) * NV < tot of the row group at xg
+  __device__ __forceinline__ void load(const T *__restrict__ xg, int tot, int lane) {
 #pragma unroll
     for (int t = 0; t < TMAX; ++t) {
       const int e = (lane + 64 * t) * NV;
-      if (e < tot) v[t] = *reinterpret_cast<const V *>(xg + e);
+      if (e < tot) v[t] = __builtin_nontemporal_load(reinterpret_cast<const V *>(xg + e));
     }
+  }
+
+  // Y[r][j] = s_j ((x[r][j] - o_j) - olo_j); FP32 paths subtract o as a hi + lo pair so that
+  // x - o_hi is exact near the optimum and y keeps its relative accuracy there.
+  __device__ __forceinline__ void stage(int tot, int D, int S, T *Y, const T *so, const T *sol, const T *ss,
+                                        int lane) const {
     const int e0 = lane * NV;
     int rr = e0 / D, jj = e0 - rr * D;
-    const int step = 64 * NV;
+    constexpr int step = 64 * NV;
     const int dr = step / D, dj = step - dr * D;
 #pragma unroll
     for (int t = 0; t < TMAX; ++t) {
       const int e = (lane + 64 * t) * NV;
       if (e < tot) {
-        const V ov = *reinterpret_cast<const V *>(so + jj);
-        const V sv = *reinterpret_cast<const V *>(ss + jj);
-        V d = v[t] - ov;
+        V d = v[t] - *reinterpret_cast<const V *>(so + jj);
         if constexpr (P != PATH_F64) d -= *reinterpret_cast<const V *>(sol + jj);
-        *reinterpret_cast<V *>(Y + rr * S + jj) = sv * d;
+        *reinterpret_cast<V *>(Y + rr * S + jj) = *reinterpret_cast<const V *>(ss + jj) * d;
       }
       jj += dj;
       rr += dr;
@@ -121,14 +114,25 @@ __device__ __forceinline__ void stage(const typename PathT<P>::T *__restrict__ x
         ++rr;
       }
     }
-  } else {
-    constexpr int TMAX = (kRowsPerWave * 128) / 64;
-    T v[TMAX];
+  }
+};
+
+// Element-wise fallback for dimensions that are not a multiple of the vector width or for
+// x pointers that are not 16-byte aligned.
+template <int P>
+struct XTileScalar {
+  using T = typename PathT<P>::T;
+  static constexpr int TMAX = (kRowsPerWave * 16 * kMaxMT) / 64;
+  T v[TMAX];
+  __device__ __forceinline__ void load(const T *__restrict__ xg, int tot, int lane) {
 #pragma unroll
     for (int t = 0; t < TMAX; ++t) {
       const int e = lane + 64 * t;
-      if (e < tot) v[t] = xg[e];
+      if (e < tot) v[t] = __builtin_nontemporal_load(xg + e);
     }
+  }
+  __device__ __forceinline__ void stage(int tot, int D, int S, T *Y, const T *so, const T *sol, const T *ss,
+                                        int lane) const {
     int rr = lane / D, jj = lane - rr * D;
     const int dr = 64 / D, dj = 64 - dr * D;
 #pragma unroll
@@ -147,24 +151,23 @@ __device__ __forceinline__ void stage(const typename PathT<P>::T *__restrict__ x
       }
     }
   }
-}
+};
 
-// Z^T = Qp Y^T for the wave's 16 rows; z[m][e] receives packed position frag_pos(m, q, e).
+// Z^T = Qp Y^T for the wave's 16 rows into acc; element e of acc[m] is packed position
+// frag_pos(m, q, e).
 template <int P>
-__device__ __forceinline__ void rotate(typename PathT<P>::T (&z)[kMaxMT][4], const DevProb &pb,
+__device__ __forceinline__ void rotate(typename PathT<P>::Acc4 (&acc)[kMaxMT], const DevProb &pb,
                                        const unsigned char *s_q, const uint16_t *s_orig,
-                                       const typename PathT<P>::T *Y, int r, int q, int lane) {
+                                       const typename PathT<P>::T *Yr, int q, int lane) {
   using T = typename PathT<P>::T;
   using Acc4 = typename PathT<P>::Acc4;
-  Acc4 acc[kMaxMT];
 #pragma unroll
   for (int m = 0; m < kMaxMT; ++m) acc[m] = Acc4{0, 0, 0, 0};
-  const T *Yr = Y + r * pb.S;
   const int4 *ktab = reinterpret_cast<const int4 *>(pb.ktab);
   for (int kt = 0; kt < pb.KT; ++kt) {
     const int4 ki = ktab[kt];  // uniform: scalar load
     if constexpr (P == PATH_SPLIT || P == PATH_SPLIT6) {
-      // this lane's 8 inputs: packed positions 32 kt + 8 q + 0..7, split into bf16 terms
+      // this lane's 8 inputs: packed positions 32 kt + 8 q + 0..7, cut into bf16 terms
       // (y - hi and the next residual are exact in FP32)
       const uint4 idx = *reinterpret_cast<const uint4 *>(s_orig + kt * 32 + q * 8);
       const uint32_t iw[4] = {idx.x, idx.y, idx.z, idx.w};
@@ -190,7 +193,7 @@ __device__ __forceinline__ void rotate(typename PathT<P>::T (&z)[kMaxMT][4], con
         if (m >= ki.x && m <= ki.y) {
           const int t = ki.z + m - ki.x;
           if constexpr (P == PATH_SPLIT6) {
-            // keep the six products of total order <= 2 in the 2^-8 splitting, smallest first
+            // the six products of total order <= 2 in the 2^-8 splitting, smallest first
             const bf16x8 ah = qf[t * 192 + lane];
             const bf16x8 am = qf[t * 192 + 64 + lane];
             const bf16x8 al = qf[t * 192 + 128 + lane];
@@ -224,18 +227,15 @@ __device__ __forceinline__ void rotate(typename PathT<P>::T (&z)[kMaxMT][4], con
       }
     }
   }
-#pragma unroll
-  for (int m = 0; m < kMaxMT; ++m)
-#pragma unroll
-    for (int e = 0; e < 4; ++e) z[m][e] = acc[m][e];
 }
 
-template <int P, int KIND>
-__global__ __launch_bounds__(256) void k_eval_resident(DevProb pb, const typename PathT<P>::T *__restrict__ x,
-                                                       typename PathT<P>::T *__restrict__ out, int n, int vec) {
+template <int P, int KIND, int ROT, typename Tile>
+__device__ __forceinline__ void eval_body(const DevProb &pb, const typename PathT<P>::T *__restrict__ x,
+                                          typename PathT<P>::T *__restrict__ out, int n) {
   using T = typename PathT<P>::T;
+  using Acc4 = typename PathT<P>::Acc4;
   extern __shared__ __align__(16) unsigned char smem[];
-  const LdsLayout L = lds_layout(P, pb);
+  const LdsLayout L = lds_layout(P, pb, blockDim.x >> 6);
   unsigned char *s_q = smem + L.q;
   T *s_o = reinterpret_cast<T *>(smem + L.o);
   T *s_ol = reinterpret_cast<T *>(smem + L.olo);
@@ -246,52 +246,62 @@ __global__ __launch_bounds__(256) void k_eval_resident(DevProb pb, const typenam
   int16_t *s_succ = reinterpret_cast<int16_t *>(smem + L.succ);
   T *s_y = reinterpret_cast<T *>(smem + L.y);
 
-  if (pb.rotated) {
+  const int D = pb.D, S = pb.S, MT = pb.MT;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nwaves = blockDim.x >> 6;
+  const int r = lane & 15, q = lane >> 4;
+  const int ngroups = (n + kRowsPerWave - 1) / kRowsPerWave;
+  const int gstride = gridDim.x * nwaves;
+  int g = blockIdx.x * nwaves + wave;
+
+  // first row group's loads go out before the tables are copied
+  Tile xt;
+  if (g < ngroups) {
+    const int row0 = g * kRowsPerWave;
+    xt.load(x + static_cast<size_t>(row0) * D, min(kRowsPerWave, n - row0) * D, lane);
+  }
+  if (ROT) {
     copy_to_lds(s_q, pb.qfrag, L.q_bytes);
     copy_to_lds(reinterpret_cast<unsigned char *>(s_orig), pb.orig, L.orig_bytes);
   }
   copy_to_lds(reinterpret_cast<unsigned char *>(s_o), pb.o, L.vec_bytes);
   if (P != PATH_F64) copy_to_lds(reinterpret_cast<unsigned char *>(s_ol), pb.olo, L.vec_bytes);
   copy_to_lds(reinterpret_cast<unsigned char *>(s_s), pb.sj, L.vec_bytes);
-  copy_to_lds(reinterpret_cast<unsigned char *>(s_coef), pb.coef, L.mp_bytes);
+  if (KindTraits<KIND>::needs_coef) copy_to_lds(reinterpret_cast<unsigned char *>(s_coef), pb.coef, L.mp_bytes);
   copy_to_lds(reinterpret_cast<unsigned char *>(s_cz), pb.cz, L.mp_bytes);
   if (KindTraits<KIND>::pairwise) copy_to_lds(reinterpret_cast<unsigned char *>(s_succ), pb.succ, L.succ_bytes);
   __syncthreads();
 
-  const int D = pb.D, S = pb.S, MT = pb.MT;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int r = lane & 15, q = lane >> 4;
   T *Y = s_y + wave * kRowsPerWave * S;
+  const T *Yr = Y + r * S;
   if (lane < kRowsPerWave) Y[lane * S + D] = T(0);  // padding slot read by the gather
   const T prm = kind_param<KIND, T>(pb.Df, pb.kparam);
 
-  const int ngroups = (n + kRowsPerWave - 1) / kRowsPerWave;
-  for (int g = blockIdx.x * kWavesPerWG + wave; g < ngroups; g += gridDim.x * kWavesPerWG) {
+  for (; g < ngroups; g += gstride) {
     const int row0 = g * kRowsPerWave;
     const int nrows = min(kRowsPerWave, n - row0);
     wave_sync();
-    stage<P>(x + static_cast<size_t>(row0) * D, nrows * D, D, S, vec != 0, Y, s_o, s_ol, s_s, lane);
+    xt.stage(nrows * D, D, S, Y, s_o, s_ol, s_s, lane);
+    // next row group's loads are in flight during everything below
+    const int gn = g + gstride;
+    if (gn < ngroups) {
+      const int rown = gn * kRowsPerWave;
+      xt.load(x + static_cast<size_t>(rown) * D, min(kRowsPerWave, n - rown) * D, lane);
+    }
     wave_sync();
 
-    T z[kMaxMT][4];
-    if (pb.rotated) {
-      rotate<P>(z, pb, s_q, s_orig, Y, r, q, lane);
+    Acc4 acc[kMaxMT];
+    if constexpr (ROT) {
+      rotate<P>(acc, pb, s_q, s_orig, Yr, q, lane);
     } else {
 #pragma unroll
       for (int m = 0; m < kMaxMT; ++m)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int p = frag_pos<P>(m, q, e);
-          z[m][e] = (m < MT && p < D) ? Y[r * S + p] : T(0);
+          acc[m][e] = (m < MT && p < D) ? Yr[p] : T(0);
         }
     }
-#pragma unroll
-    for (int m = 0; m < kMaxMT; ++m)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int p = frag_pos<P>(m, q, e);
-        if (m < MT) z[m][e] += s_cz[p];
-      }
 
     Acc<T> a;
     a.init();
@@ -302,7 +312,7 @@ __global__ __launch_bounds__(256) void k_eval_resident(DevProb pb, const typenam
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int p = frag_pos<P>(m, q, e);
-          if (m < MT && p < D) Y[r * S + p] = z[m][e];
+          if (m < MT && p < D) Y[r * S + p] = acc[m][e] + s_cz[p];
         }
       wave_sync();
 #pragma unroll
@@ -312,7 +322,7 @@ __global__ __launch_bounds__(256) void k_eval_resident(DevProb pb, const typenam
           const int p = frag_pos<P>(m, q, e);
           if (m < MT && p < D) {
             const int sp = s_succ[p];
-            if (sp >= 0) phi<KIND, T>(a, z[m][e], Y[r * S + sp], T(0), prm);
+            if (sp >= 0) phi<KIND, T>(a, Yr[p], Yr[sp], T(0), prm);
           }
         }
     } else {
@@ -323,7 +333,7 @@ __global__ __launch_bounds__(256) void k_eval_resident(DevProb pb, const typenam
           const int p = frag_pos<P>(m, q, e);
           if (m < MT && p < D) {
             const T cf = KindTraits<KIND>::needs_coef ? s_coef[p] : T(0);
-            phi<KIND, T>(a, z[m][e], T(0), cf, prm);
+            phi<KIND, T>(a, T(acc[m][e]) + s_cz[p], T(0), cf, prm);
           }
         }
     }
@@ -344,56 +354,21 @@ __global__ __launch_bounds__(256) void k_eval_resident(DevProb pb, const typenam
   }
 }
 
-// ---- launch table ----------------------------------------------------------------------
+template <int P, int KIND, int ROT, int VEC>
+__global__ __launch_bounds__(512) void k_eval_resident(DevProb pb, const typename PathT<P>::T *__restrict__ x,
+                                                       typename PathT<P>::T *__restrict__ out, int n) {
+  if constexpr (VEC)
+    eval_body<P, KIND, ROT, XTile<P>>(pb, x, out, n);
+  else
+    eval_body<P, KIND, ROT, XTileScalar<P>>(pb, x, out, n);
+}
 
+// Kernel table of one path: index ((kind * 2) + rot) * 2 + vec.
 template <int P, int... Ks>
-static const void *const *kernel_table(std::integer_sequence<int, Ks...>) {
-  static const void *const tab[] = {reinterpret_cast<const void *>(&k_eval_resident<P, Ks>)...};
+const void *const *resident_table(std::integer_sequence<int, Ks...>) {
+  static const void *const tab[] = {
+      (reinterpret_cast<const void *>(&k_eval_resident<P, Ks / 4, (Ks / 2) % 2, Ks % 2>))...};
   return tab;
-}
-
-static const void *resident_kernel(int path, int kind) {
-  if (kind < 0 || kind >= K_COUNT) return nullptr;
-  auto seq = std::make_integer_sequence<int, K_COUNT>{};
-  switch (path) {
-    case PATH_SPLIT: return kernel_table<PATH_SPLIT>(seq)[kind];
-    case PATH_F32: return kernel_table<PATH_F32>(seq)[kind];
-    case PATH_F64: return kernel_table<PATH_F64>(seq)[kind];
-    case PATH_SPLIT6: return kernel_table<PATH_SPLIT6>(seq)[kind];
-    default: return nullptr;
-  }
-}
-
-int resident_grid(int path, const DevProb &pb, int n, int num_cu) {
-  const LdsLayout L = lds_layout(path, pb);
-  const void *fn = resident_kernel(path, pb.kind);
-  int occ = 0;
-  if (fn == nullptr ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, 64 * kWavesPerWG, static_cast<size_t>(L.total)) !=
-          hipSuccess)
-    occ = 1;
-  if (occ < 1) occ = 1;
-  const int groups = (n + kRowsPerWave - 1) / kRowsPerWave;
-  const int need = (groups + kWavesPerWG - 1) / kWavesPerWG;
-  const int cap = occ * num_cu;
-  return need < cap ? (need > 0 ? need : 1) : cap;
-}
-
-hipError_t launch_resident(int path, const DevProb &pb, const void *x, void *out, int n, int grid, hipStream_t st) {
-  const void *fn = resident_kernel(path, pb.kind);
-  if (fn == nullptr) return hipErrorInvalidValue;
-  const LdsLayout L = lds_layout(path, pb);
-  if (L.total > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, L.total);
-    if (e != hipSuccess) return e;
-  }
-  const size_t esz = path == PATH_F64 ? 8 : 4;
-  int vec = ((pb.D % static_cast<int>(16 / esz)) == 0 && (reinterpret_cast<uintptr_t>(x) % 16) == 0) ? 1 : 0;
-  DevProb arg = pb;
-  const void *xa = x;
-  void *oa = out;
-  void *args[] = {&arg, &xa, &oa, &n, &vec};
-  return hipLaunchKernel(fn, dim3(grid), dim3(64 * kWavesPerWG), args, static_cast<size_t>(L.total), st);
 }
 
 }  // namespace curob

@@ -13,14 +13,18 @@ namespace curob {
 struct LdsLayout {
   int q, o, olo, s, orig, coef, cz, succ, y;  // byte offsets
   int q_bytes, vec_bytes, orig_bytes, mp_bytes, succ_bytes, y_bytes;
+  int fixed;  // bytes before the per-wave slices
   int total;
 };
 
 __host__ __device__ inline int round16(int b) { return (b + 15) & ~15; }
 
+constexpr int kMaxLdsBytes = 160 * 1024;  // LDS per workgroup on gfx950
+constexpr int kMaxWavesPerWG = 8;
+
 // LDS carve of the resident kernel: rotation tiles, per-variable tables, per-position tables,
 // then one 16 x S slice per wave for the staged rows.
-__host__ __device__ inline LdsLayout lds_layout(int path, const DevProb &pb) {
+__host__ __device__ inline LdsLayout lds_layout(int path, const DevProb &pb, int nwaves) {
   const int esz = path == PATH_F64 ? 8 : 4;
   const int kw = kw_of(path);
   LdsLayout L;
@@ -29,7 +33,7 @@ __host__ __device__ inline LdsLayout lds_layout(int path, const DevProb &pb) {
   L.vec_bytes = round16(pb.D * esz);
   L.mp_bytes = round16(16 * pb.MT * esz);
   L.succ_bytes = round16(16 * pb.MT * 2);
-  L.y_bytes = kWavesPerWG * kRowsPerWave * pb.S * esz;
+  L.y_bytes = kRowsPerWave * pb.S * esz;
   int off = 0;
   L.q = off;
   off += L.q_bytes;
@@ -48,15 +52,23 @@ __host__ __device__ inline LdsLayout lds_layout(int path, const DevProb &pb) {
   L.succ = off;
   off += L.succ_bytes;
   L.y = off;
-  off += round16(L.y_bytes);
+  L.fixed = off;
+  off += round16(L.y_bytes) * nwaves;
   L.total = off;
   return L;
 }
 
-// Resident kernel (dimension <= 128): evaluates n rows of x (device, row-major) into out.
-hipError_t launch_resident(int path, const DevProb &pb, const void *x, void *out, int n, int grid, hipStream_t st);
+// Launch shape of the resident kernel for one problem: waves per workgroup (as many as the
+// LDS slices allow, up to 8) and a persistent grid of at most `occupancy x CUs` workgroups.
+struct LaunchShape {
+  int waves;
+  int grid;
+  int lds;
+};
+LaunchShape resident_shape(int path, const DevProb &pb, int n, int num_cu);
 
-// Occupancy-derived workgroup count for the resident kernel.
-int resident_grid(int path, const DevProb &pb, int n, int num_cu);
+// Resident kernel (dimension <= 128): evaluates n rows of x (device, row-major) into out.
+hipError_t launch_resident(int path, const DevProb &pb, const void *x, void *out, int n, const LaunchShape &ls,
+                           hipStream_t st);
 
 }  // namespace curob
