@@ -20,35 +20,39 @@ inline constexpr bool is_split(int path) { return path == PATH_SPLIT || path == 
 inline constexpr int split_terms(int path) { return path == PATH_SPLIT6 ? 3 : 2; }
 
 // Tile geometry of the block-diagonal rotation in packed (group-ordered) variable space.
-// The MFMA computes Z^T = Qp * Y^T tile by tile: Qp is the packed block-diagonal matrix,
+// The MFMA computes Z^T = Qp Y^T tile by tile: Qp is the packed block-diagonal matrix,
 // m-tiles are 16 output positions, k-tiles are KW input positions (32 for BF16, 4 for FP32/64).
-constexpr int kMaxMT = 8;         // m-tiles supported by the resident kernel (dimension <= 128)
-constexpr int kRowsPerWave = 16;  // population rows per wave iteration (the MFMA N dimension)
-constexpr int kWavesPerWG = 4;
+constexpr int kMaxMT = 8;          // m-tiles supported by the resident kernel (dimension <= 128)
+constexpr int kRowsPerBlock = 16;  // population rows per MFMA column block (the MFMA N dimension)
 
 inline constexpr int kw_of(int path) { return is_split(path) ? 32 : 4; }
+// 16-row column blocks a wave evaluates per iteration: two on the FP32 paths, so every rotation
+// tile read from LDS feeds two MFMAs; one on the FP64 path (register budget).
+inline constexpr int blocks_of(int path) { return path == PATH_F64 ? 1 : 2; }
 
 struct DevProb {
   // every pointer is device memory owned by the library
-  const void *o;          // shift, original order, D entries (float or double per path)
-  const void *olo;        // FP32 paths: o - float(o), so (x - o_hi) - o_lo keeps y accurate near o
-  const void *sj;         // scale s per original variable, D entries
-  const uint16_t *orig;   // packed position -> original variable; KT*KW entries, padding -> D
-  const void *coef;       // per packed position coefficient, 16*MT entries
-  const void *cz;         // per packed position post-offset c, 16*MT entries
-  const int16_t *succ;    // per packed position: packed position of the formula successor or -1
-  const void *qfrag;      // nonzero rotation tiles in MFMA operand order (path-specific layout)
-  const int *ktab;        // per k-tile: first m-tile, last m-tile, first tile index, 0
-  int D;                  // dimension
-  int S;                  // LDS row stride in elements (>= D+1, 4*odd)
-  int KT;                 // k-tiles
-  int MT;                 // m-tiles
-  int ntiles;             // nonzero tiles
-  int rotated;            // 0: z = y + c directly
-  int kind;               // formula family (problem.h Kind)
-  int Df;                 // dimension seen by the formula
-  double bias;            // f_opt
-  double kparam;          // family parameter (Katsuura exponent 10/D^1.2)
+  const void *oh;        // shift rounded to the path's type, original variable order, D entries
+  const uint16_t *goff;  // packed position -> byte offset of its variable in an LDS row; KT*KW
+                         // entries, padding -> the zero slot at D
+  const void *cz;        // per packed position (16*MT entries) offset c' added after the rotation:
+                         // c minus the rotated, scaled rounding error of the shift on FP32 paths
+  const void *coef;      // per packed position coefficient (elliptic weights, 1/sqrt(i), ...)
+  const int16_t *succ;   // per packed position: packed position of the formula successor or -1
+  const void *qfrag;     // nonzero tiles of s*Qp in MFMA operand order (path-specific layout)
+  const int *mtab;       // per m-tile: first k-tile, last k-tile, first tile index, 0
+  int D;                 // dimension
+  int S;                 // LDS row stride in elements (4*odd, >= D+1 and >= 16*MT)
+  int KT;                // k-tiles
+  int MT;                // m-tiles
+  int ntiles;            // nonzero tiles
+  int rotated;           // 0: z = s*y + c' directly
+  int kind;              // formula family (problem.h Kind)
+  int Df;                // dimension seen by the formula
+  double bias;           // f_opt
+  double kparam;         // family parameter (Katsuura exponent 10/D^1.2)
+  double scale;          // s, applied in the formula phase when the problem is unrotated
+  double padc[3];        // what the 16*MT - D padded positions add to each sum, removed at the end
 };
 
 }  // namespace curob

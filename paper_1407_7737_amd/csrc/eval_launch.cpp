@@ -36,7 +36,8 @@ LaunchShape resident_shape(int path, const DevProb &pb, int n, int num_cu) {
   int waves = (kMaxLdsBytes - one.fixed) / slice;
   if (waves > kMaxWavesPerWG) waves = kMaxWavesPerWG;
   if (waves < 1) waves = 1;
-  const int groups = (n + kRowsPerWave - 1) / kRowsPerWave;
+  const int rows = kRowsPerBlock * blocks_of(path);
+  const int groups = (n + rows - 1) / rows;
   // small populations: fewer waves per workgroup spread the groups over more CUs
   while (waves > 1 && (groups + waves - 1) / waves < num_cu) waves >>= 1;
   ls.waves = waves;

@@ -1,23 +1,29 @@
 // eval_resident.h -- fused evaluation kernel for basic functions of dimension <= 128.
 //
-// Each wave evaluates 16 candidate rows at a time and loops over row groups (grid-stride):
-//   1. stage   the 16 x D block of x (contiguous in HBM) was loaded into registers during the
-//              previous iteration; form y = s (x - o) and store it row-major in the wave's LDS
-//              slice, then immediately issue the loads of the wave's next row group so that
-//              HBM traffic overlaps everything below;
-//   2. rotate  Z^T = Qp Y^T on the matrix cores over the nonzero tiles of the packed
+// Each wave evaluates 16 * NB candidate rows per iteration (NB column blocks of 16) and loops
+// over row groups (grid-stride):
+//   1. stage   the rows' x (contiguous in HBM) arrived in registers during the previous
+//              iteration through bounds-checked buffer loads; y = x - o_hi goes to the wave's
+//              LDS slice, and the loads of the next row group are issued at once so that HBM
+//              traffic overlaps everything below;
+//   2. rotate  Z^T = (s Qp) Y^T on the matrix cores over the nonzero tiles of the packed
 //              block-diagonal rotation (Sec. 1.2: three random variable groups, one orthonormal
 //              block each).  The B operand is gathered from LDS in group order; on the split
-//              paths each y is cut into bf16 terms and the products accumulate in FP32;
-//   3. phi     add the offset c and apply the formula straight from the accumulator fragment
-//              (pairwise families first exchange z through LDS to reach z_{i+1});
-//   4. reduce  per-lane compensated sums, a two-step cross-lane combine, finalise, store.
+//              paths each y is cut into bf16 terms and the products accumulate in FP32.  Every
+//              rotation tile read from LDS feeds all NB column blocks;
+//   3. phi     z = acc + c' and the formula, straight from the accumulator fragment (pairwise
+//              families first exchange z through LDS to reach z_{i+1}); padded positions are
+//              laid out so that they add exactly known constants, removed at the end;
+//   4. reduce  groups of four terms summed plainly, then Kahan-compensated per lane, a two-step
+//              cross-lane combine, finalise, store.
 // The rotation tiles and per-position tables sit in LDS once per workgroup.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
+#include <utility>
 
 #include "devprob.h"
 #include "formulas.h"
@@ -29,35 +35,28 @@ typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 template <int P>
 struct PathT {
   using T = float;
-  using V = f32x4;  // 16-byte staging vector
+  using V = f32x4;  // one 16-byte load
   using Acc4 = f32x4;
-  static constexpr int KW = 32;
-};
-template <>
-struct PathT<PATH_F32> {
-  using T = float;
-  using V = f32x4;
-  using Acc4 = f32x4;
-  static constexpr int KW = 4;
 };
 template <>
 struct PathT<PATH_F64> {
   using T = double;
   using V = f64x2;
   using Acc4 = f64x4;
-  static constexpr int KW = 4;
 };
 
 // Packed position held in accumulator element e of m-tile m by lane group q (= lane / 16).
 // BF16 16x16x32 and FP32 16x16x4 place output row 4q+e in element e; FP64 16x16x4 places
-// output row 4e+q there.
-template <int P>
+// output row 4e+q there.  Unrotated problems use the first layout on every path.
+template <int P, int ROT>
 __device__ __forceinline__ int frag_pos(int m, int q, int e) {
-  if constexpr (P == PATH_F64) return 16 * m + 4 * e + q;
+  if constexpr (P == PATH_F64 && ROT) return 16 * m + 4 * e + q;
   else return 16 * m + 4 * q + e;
 }
 
@@ -73,39 +72,59 @@ __device__ __forceinline__ void copy_to_lds(unsigned char *dst, const void *src,
   for (int i = threadIdx.x; i < (bytes >> 4); i += blockDim.x) d[i] = s[i];
 }
 
-// Registers holding one wave's 16 x D slice of x between its load and its staging.
-template <int P>
+// Buffer resource over rows [row0, n) of x: loads past the end return zeros instead of
+// faulting, so the last, partial row group needs no per-lane predicate.
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rows_rsrc(const T *x, int row0, int n, int D) {
+  const long long bytes = static_cast<long long>(n - row0) * D * static_cast<long long>(sizeof(T));
+  const int nb = bytes > 0x7ffffff0LL ? 0x7ffffff0 : static_cast<int>(bytes);
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(x + static_cast<size_t>(row0) * D), (short)0, nb,
+                                           0x00020000);
+}
+
+// Registers holding a wave's rows between their load and their staging: 16-byte loads when
+// the dimension is a multiple of the vector width (VEC), element loads otherwise.
+template <int P, int VEC>
 struct XTile {
   using T = typename PathT<P>::T;
   using V = typename PathT<P>::V;
-  static constexpr int NV = 16 / sizeof(T);
-  static constexpr int TMAX = (kRowsPerWave * 16 * kMaxMT) / (64 * NV);
-  V v[TMAX];
+  static constexpr int ROWS = kRowsPerBlock * blocks_of(P);
+  static constexpr int NV = VEC ? 16 / static_cast<int>(sizeof(T)) : 1;  // elements per load
+  static constexpr int CMAX = ROWS * 16 * kMaxMT / (64 * NV);            // loads per lane, D <= 128
+  using L = typename std::conditional<VEC, V, T>::type;
+  L v[CMAX];
 
-  // 16-byte loads of elements (lane + 64 t) * NV < tot of the row group at xg
-  __device__ __forceinline__ void load(const T *__restrict__ xg, int tot, int lane) {
+  __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t rs, int nload, int lane) {
 #pragma unroll
-    for (int t = 0; t < TMAX; ++t) {
-      const int e = (lane + 64 * t) * NV;
-      if (e < tot) v[t] = __builtin_nontemporal_load(reinterpret_cast<const V *>(xg + e));
+    for (int t = 0; t < CMAX; ++t) {
+      if (t < nload) {
+        const int off = (lane + 64 * t) * NV * static_cast<int>(sizeof(T));
+        if constexpr (VEC) {
+          v[t] = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+        } else if constexpr (sizeof(T) == 8) {
+          v[t] = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+        } else {
+          v[t] = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+        }
+      }
     }
   }
 
-  // Y[r][j] = s_j ((x[r][j] - o_j) - olo_j); FP32 paths subtract o as a hi + lo pair so that
-  // x - o_hi is exact near the optimum and y keeps its relative accuracy there.
-  __device__ __forceinline__ void stage(int tot, int D, int S, T *Y, const T *so, const T *sol, const T *ss,
-                                        int lane) const {
+  // Y[r][j] = x[r][j] - o_hi[j] for the wave's rows; elements past the last row land in the
+  // spill row ROWS of the slice.
+  __device__ __forceinline__ void stage(int nload, int D, int S, T *Y, const T *oh, int lane) const {
     const int e0 = lane * NV;
     int rr = e0 / D, jj = e0 - rr * D;
     constexpr int step = 64 * NV;
     const int dr = step / D, dj = step - dr * D;
 #pragma unroll
-    for (int t = 0; t < TMAX; ++t) {
-      const int e = (lane + 64 * t) * NV;
-      if (e < tot) {
-        V d = v[t] - *reinterpret_cast<const V *>(so + jj);
-        if constexpr (P != PATH_F64) d -= *reinterpret_cast<const V *>(sol + jj);
-        *reinterpret_cast<V *>(Y + rr * S + jj) = *reinterpret_cast<const V *>(ss + jj) * d;
+    for (int t = 0; t < CMAX; ++t) {
+      if (t < nload) {
+        const int ra = rr < ROWS ? rr : ROWS;
+        if constexpr (VEC)
+          *reinterpret_cast<V *>(Y + ra * S + jj) = v[t] - *reinterpret_cast<const V *>(oh + jj);
+        else
+          Y[ra * S + jj] = v[t] - oh[jj];
       }
       jj += dj;
       rr += dr;
@@ -117,250 +136,308 @@ struct XTile {
   }
 };
 
-// Element-wise fallback for dimensions that are not a multiple of the vector width or for
-// x pointers that are not 16-byte aligned.
+// Per-path operand types of the rotation: B fragments for every k-tile stay in registers
+// ("B stationary") while the m-tiles stream past them.
 template <int P>
-struct XTileScalar {
-  using T = typename PathT<P>::T;
-  static constexpr int TMAX = (kRowsPerWave * 16 * kMaxMT) / 64;
-  T v[TMAX];
-  __device__ __forceinline__ void load(const T *__restrict__ xg, int tot, int lane) {
-#pragma unroll
-    for (int t = 0; t < TMAX; ++t) {
-      const int e = lane + 64 * t;
-      if (e < tot) v[t] = __builtin_nontemporal_load(xg + e);
-    }
-  }
-  __device__ __forceinline__ void stage(int tot, int D, int S, T *Y, const T *so, const T *sol, const T *ss,
-                                        int lane) const {
-    int rr = lane / D, jj = lane - rr * D;
-    const int dr = 64 / D, dj = 64 - dr * D;
-#pragma unroll
-    for (int t = 0; t < TMAX; ++t) {
-      const int e = lane + 64 * t;
-      if (e < tot) {
-        T d = v[t] - so[jj];
-        if constexpr (P != PATH_F64) d -= sol[jj];
-        Y[rr * S + jj] = ss[jj] * d;
-      }
-      jj += dj;
-      rr += dr;
-      if (jj >= D) {
-        jj -= D;
-        ++rr;
-      }
-    }
-  }
+struct RotOps;
+template <>
+struct RotOps<PATH_SPLIT> {
+  static constexpr int KTMAX = 16 * kMaxMT / 32;  // k-tiles of 32 for dimension <= 128
+  static constexpr int NTERM = 2;
+  using Frag = bf16x8;
+};
+template <>
+struct RotOps<PATH_SPLIT6> {
+  static constexpr int KTMAX = 16 * kMaxMT / 32;
+  static constexpr int NTERM = 3;
+  using Frag = bf16x8;
+};
+template <>
+struct RotOps<PATH_F32> {
+  static constexpr int KTMAX = 16 * kMaxMT / 4;  // k-tiles of 4
+  static constexpr int NTERM = 1;
+  using Frag = float;
+};
+template <>
+struct RotOps<PATH_F64> {
+  static constexpr int KTMAX = 16 * kMaxMT / 4;
+  static constexpr int NTERM = 1;
+  using Frag = double;
 };
 
-// Z^T = Qp Y^T for the wave's 16 rows into acc; element e of acc[m] is packed position
-// frag_pos(m, q, e).
+// Gathers this lane's B operand of every k-tile and column block from the staged rows (packed
+// order via the byte offsets s_goff) and, on the split paths, cuts each y into bf16 terms
+// (y - hi and the next residual are exact in FP32).  Yb: row r of column block 0.
 template <int P>
-__device__ __forceinline__ void rotate(typename PathT<P>::Acc4 (&acc)[kMaxMT], const DevProb &pb,
-                                       const unsigned char *s_q, const uint16_t *s_orig,
-                                       const typename PathT<P>::T *Yr, int q, int lane) {
-  using T = typename PathT<P>::T;
-  using Acc4 = typename PathT<P>::Acc4;
+__device__ __forceinline__ void gather_b(typename RotOps<P>::Frag (&bf)[RotOps<P>::NTERM][blocks_of(P)][RotOps<P>::KTMAX],
+                                         int KT, const uint16_t *s_goff, const unsigned char *Yb, int bstride,
+                                         int q) {
+  using R = RotOps<P>;
+  constexpr int NB = blocks_of(P);
 #pragma unroll
-  for (int m = 0; m < kMaxMT; ++m) acc[m] = Acc4{0, 0, 0, 0};
-  const int4 *ktab = reinterpret_cast<const int4 *>(pb.ktab);
-  for (int kt = 0; kt < pb.KT; ++kt) {
-    const int4 ki = ktab[kt];  // uniform: scalar load
-    if constexpr (P == PATH_SPLIT || P == PATH_SPLIT6) {
-      // this lane's 8 inputs: packed positions 32 kt + 8 q + 0..7, cut into bf16 terms
-      // (y - hi and the next residual are exact in FP32)
-      const uint4 idx = *reinterpret_cast<const uint4 *>(s_orig + kt * 32 + q * 8);
-      const uint32_t iw[4] = {idx.x, idx.y, idx.z, idx.w};
-      bf16x8 bh, bm, bl;
+  for (int kt = 0; kt < R::KTMAX; ++kt) {
+    if (kt < KT) {
+      if constexpr (is_split(P)) {
+        const uint4 idx = *reinterpret_cast<const uint4 *>(s_goff + kt * 32 + q * 8);
+        const uint32_t iw[4] = {idx.x, idx.y, idx.z, idx.w};
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const uint32_t j = (iw[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
-        const float y = Yr[j];
-        const __bf16 h = (__bf16)y;
-        const float r1 = y - (float)h;
-        bh[e] = h;
-        if constexpr (P == PATH_SPLIT6) {
-          const __bf16 mm = (__bf16)r1;
-          bm[e] = mm;
-          bl[e] = (__bf16)(r1 - (float)mm);
-        } else {
-          bl[e] = (__bf16)r1;
-        }
-      }
-      const bf16x8 *qf = reinterpret_cast<const bf16x8 *>(s_q);
+        for (int e = 0; e < 8; ++e) {
+          const uint32_t off = (iw[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
 #pragma unroll
-      for (int m = 0; m < kMaxMT; ++m) {
-        if (m >= ki.x && m <= ki.y) {
-          const int t = ki.z + m - ki.x;
-          if constexpr (P == PATH_SPLIT6) {
-            // the six products of total order <= 2 in the 2^-8 splitting, smallest first
-            const bf16x8 ah = qf[t * 192 + lane];
-            const bf16x8 am = qf[t * 192 + 64 + lane];
-            const bf16x8 al = qf[t * 192 + 128 + lane];
-            acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[m], 0, 0, 0);
-            acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm, acc[m], 0, 0, 0);
-            acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[m], 0, 0, 0);
-            acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh, acc[m], 0, 0, 0);
-            acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm, acc[m], 0, 0, 0);
-            acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[m], 0, 0, 0);
-          } else {
-            const bf16x8 ah = qf[t * 128 + lane];
-            const bf16x8 al = qf[t * 128 + 64 + lane];
-            acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[m], 0, 0, 0);
-            acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[m], 0, 0, 0);
-            acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[m], 0, 0, 0);
+          for (int b = 0; b < NB; ++b) {
+            const float y = *reinterpret_cast<const float *>(Yb + b * bstride + off);
+            const __bf16 h = (__bf16)y;
+            const float r1 = y - (float)h;
+            bf[0][b][kt][e] = h;
+            if constexpr (R::NTERM == 3) {
+              const __bf16 mm = (__bf16)r1;
+              bf[1][b][kt][e] = mm;
+              bf[2][b][kt][e] = (__bf16)(r1 - (float)mm);
+            } else {
+              bf[1][b][kt][e] = (__bf16)r1;
+            }
           }
         }
-      }
-    } else {
-      const T b = Yr[s_orig[kt * 4 + q]];
-      const T *qf = reinterpret_cast<const T *>(s_q);
+      } else {
+        const uint32_t off = s_goff[kt * 4 + q];
 #pragma unroll
-      for (int m = 0; m < kMaxMT; ++m) {
-        if (m >= ki.x && m <= ki.y) {
-          const T a = qf[(ki.z + m - ki.x) * 64 + lane];
+        for (int b = 0; b < NB; ++b)
+          bf[0][b][kt] = *reinterpret_cast<const typename R::Frag *>(Yb + b * bstride + off);
+      }
+    }
+  }
+}
+
+// One m-tile of Z^T = (s Qp) Y^T for all column blocks: acc[b] element e is packed position
+// frag_pos(m, q, e).  mi = (first k-tile, last k-tile, first tile index) of m-tile m.
+template <int P>
+__device__ __forceinline__ void mtile(typename PathT<P>::Acc4 (&acc)[blocks_of(P)], int4 mi,
+                                      const typename RotOps<P>::Frag (&bf)[RotOps<P>::NTERM][blocks_of(P)][RotOps<P>::KTMAX],
+                                      const unsigned char *s_q, int lane) {
+  using R = RotOps<P>;
+  using Acc4 = typename PathT<P>::Acc4;
+  constexpr int NB = blocks_of(P);
+#pragma unroll
+  for (int b = 0; b < NB; ++b) acc[b] = Acc4{0, 0, 0, 0};
+#pragma unroll
+  for (int kt = 0; kt < R::KTMAX; ++kt) {
+    if (kt >= mi.x && kt <= mi.y) {
+      const int t = mi.z + kt - mi.x;
+      if constexpr (P == PATH_SPLIT6) {
+        // the six products of total order <= 2 in the 2^-8 splitting, smallest first
+        const bf16x8 *qf = reinterpret_cast<const bf16x8 *>(s_q) + t * 192 + lane;
+        const bf16x8 ah = qf[0], am = qf[64], al = qf[128];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bf[0][b][kt], acc[b], 0, 0, 0);
+          acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bf[1][b][kt], acc[b], 0, 0, 0);
+          acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bf[2][b][kt], acc[b], 0, 0, 0);
+          acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bf[0][b][kt], acc[b], 0, 0, 0);
+          acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bf[1][b][kt], acc[b], 0, 0, 0);
+          acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bf[0][b][kt], acc[b], 0, 0, 0);
+        }
+      } else if constexpr (P == PATH_SPLIT) {
+        const bf16x8 *qf = reinterpret_cast<const bf16x8 *>(s_q) + t * 128 + lane;
+        const bf16x8 ah = qf[0], al = qf[64];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bf[0][b][kt], acc[b], 0, 0, 0);
+          acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bf[1][b][kt], acc[b], 0, 0, 0);
+          acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bf[0][b][kt], acc[b], 0, 0, 0);
+        }
+      } else {
+        const auto a = reinterpret_cast<const typename R::Frag *>(s_q)[t * 64 + lane];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
           if constexpr (P == PATH_F64)
-            acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[m], 0, 0, 0);
+            acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bf[0][b][kt], acc[b], 0, 0, 0);
           else
-            acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[m], 0, 0, 0);
+            acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bf[0][b][kt], acc[b], 0, 0, 0);
         }
       }
     }
   }
 }
 
-template <int P, int KIND, int ROT, typename Tile>
-__device__ __forceinline__ void eval_body(const DevProb &pb, const typename PathT<P>::T *__restrict__ x,
-                                          typename PathT<P>::T *__restrict__ out, int n) {
-  using T = typename PathT<P>::T;
-  using Acc4 = typename PathT<P>::Acc4;
-  extern __shared__ __align__(16) unsigned char smem[];
-  const LdsLayout L = lds_layout(P, pb, blockDim.x >> 6);
-  unsigned char *s_q = smem + L.q;
-  T *s_o = reinterpret_cast<T *>(smem + L.o);
-  T *s_ol = reinterpret_cast<T *>(smem + L.olo);
-  T *s_s = reinterpret_cast<T *>(smem + L.s);
-  uint16_t *s_orig = reinterpret_cast<uint16_t *>(smem + L.orig);
-  T *s_coef = reinterpret_cast<T *>(smem + L.coef);
-  T *s_cz = reinterpret_cast<T *>(smem + L.cz);
-  int16_t *s_succ = reinterpret_cast<int16_t *>(smem + L.succ);
-  T *s_y = reinterpret_cast<T *>(smem + L.y);
-
-  const int D = pb.D, S = pb.S, MT = pb.MT;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nwaves = blockDim.x >> 6;
-  const int r = lane & 15, q = lane >> 4;
-  const int ngroups = (n + kRowsPerWave - 1) / kRowsPerWave;
-  const int gstride = gridDim.x * nwaves;
-  int g = blockIdx.x * nwaves + wave;
-
-  // first row group's loads go out before the tables are copied
-  Tile xt;
-  if (g < ngroups) {
-    const int row0 = g * kRowsPerWave;
-    xt.load(x + static_cast<size_t>(row0) * D, min(kRowsPerWave, n - row0) * D, lane);
-  }
-  if (ROT) {
-    copy_to_lds(s_q, pb.qfrag, L.q_bytes);
-    copy_to_lds(reinterpret_cast<unsigned char *>(s_orig), pb.orig, L.orig_bytes);
-  }
-  copy_to_lds(reinterpret_cast<unsigned char *>(s_o), pb.o, L.vec_bytes);
-  if (P != PATH_F64) copy_to_lds(reinterpret_cast<unsigned char *>(s_ol), pb.olo, L.vec_bytes);
-  copy_to_lds(reinterpret_cast<unsigned char *>(s_s), pb.sj, L.vec_bytes);
-  if (KindTraits<KIND>::needs_coef) copy_to_lds(reinterpret_cast<unsigned char *>(s_coef), pb.coef, L.mp_bytes);
-  copy_to_lds(reinterpret_cast<unsigned char *>(s_cz), pb.cz, L.mp_bytes);
-  if (KindTraits<KIND>::pairwise) copy_to_lds(reinterpret_cast<unsigned char *>(s_succ), pb.succ, L.succ_bytes);
-  __syncthreads();
-
-  T *Y = s_y + wave * kRowsPerWave * S;
-  const T *Yr = Y + r * S;
-  if (lane < kRowsPerWave) Y[lane * S + D] = T(0);  // padding slot read by the gather
-  const T prm = kind_param<KIND, T>(pb.Df, pb.kparam);
-
-  for (; g < ngroups; g += gstride) {
-    const int row0 = g * kRowsPerWave;
-    const int nrows = min(kRowsPerWave, n - row0);
-    wave_sync();
-    xt.stage(nrows * D, D, S, Y, s_o, s_ol, s_s, lane);
-    // next row group's loads are in flight during everything below
-    const int gn = g + gstride;
-    if (gn < ngroups) {
-      const int rown = gn * kRowsPerWave;
-      xt.load(x + static_cast<size_t>(rown) * D, min(kRowsPerWave, n - rown) * D, lane);
-    }
-    wave_sync();
-
-    Acc4 acc[kMaxMT];
-    if constexpr (ROT) {
-      rotate<P>(acc, pb, s_q, s_orig, Yr, q, lane);
-    } else {
+// The four packed positions frag_pos(m, q, 0..3) of a row as one vector from LDS (unrotated
+// layout: consecutive, 16-byte aligned because S and 16 m + 4 q are multiples of 4).
+template <typename T>
+__device__ __forceinline__ void read4(T (&v)[4], const T *row, int p0) {
+  if constexpr (sizeof(T) == 4) {
+    const f32x4 t = *reinterpret_cast<const f32x4 *>(row + p0);
 #pragma unroll
-      for (int m = 0; m < kMaxMT; ++m)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int p = frag_pos<P>(m, q, e);
-          acc[m][e] = (m < MT && p < D) ? Yr[p] : T(0);
-        }
-    }
-
-    Acc<T> a;
-    a.init();
-    if constexpr (KindTraits<KIND>::pairwise) {
-      wave_sync();
-#pragma unroll
-      for (int m = 0; m < kMaxMT; ++m)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int p = frag_pos<P>(m, q, e);
-          if (m < MT && p < D) Y[r * S + p] = acc[m][e] + s_cz[p];
-        }
-      wave_sync();
-#pragma unroll
-      for (int m = 0; m < kMaxMT; ++m)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int p = frag_pos<P>(m, q, e);
-          if (m < MT && p < D) {
-            const int sp = s_succ[p];
-            if (sp >= 0) phi<KIND, T>(a, Yr[p], Yr[sp], T(0), prm);
-          }
-        }
-    } else {
-#pragma unroll
-      for (int m = 0; m < kMaxMT; ++m)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int p = frag_pos<P>(m, q, e);
-          if (m < MT && p < D) {
-            const T cf = KindTraits<KIND>::needs_coef ? s_coef[p] : T(0);
-            phi<KIND, T>(a, T(acc[m][e]) + s_cz[p], T(0), cf, prm);
-          }
-        }
-    }
-
-    // combine the four lanes that hold the same row (lane, lane^16, lane^32, lane^48)
-#pragma unroll
-    for (int sh = 16; sh <= 32; sh <<= 1) {
-      T s[3], c[3];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        s[k] = __shfl_xor(a.s[k], sh, 64);
-        c[k] = __shfl_xor(a.c[k], sh, 64);
-      }
-      const T p = __shfl_xor(a.p, sh, 64);
-      acc_merge(a, s, c, p);
-    }
-    if (q == 0 && r < nrows) out[row0 + r] = finalize<KIND, T>(a, pb.Df) + T(pb.bias);
+    for (int e = 0; e < 4; ++e) v[e] = t[e];
+  } else {
+    const f64x2 t0 = *reinterpret_cast<const f64x2 *>(row + p0);
+    const f64x2 t1 = *reinterpret_cast<const f64x2 *>(row + p0 + 2);
+    v[0] = t0[0];
+    v[1] = t0[1];
+    v[2] = t1[0];
+    v[3] = t1[1];
   }
 }
 
 template <int P, int KIND, int ROT, int VEC>
 __global__ __launch_bounds__(512) void k_eval_resident(DevProb pb, const typename PathT<P>::T *__restrict__ x,
                                                        typename PathT<P>::T *__restrict__ out, int n) {
-  if constexpr (VEC)
-    eval_body<P, KIND, ROT, XTile<P>>(pb, x, out, n);
-  else
-    eval_body<P, KIND, ROT, XTileScalar<P>>(pb, x, out, n);
+  using T = typename PathT<P>::T;
+  using Acc4 = typename PathT<P>::Acc4;
+  using Tile = XTile<P, VEC>;
+  using KT_ = KindTraits<KIND>;
+  using R = RotOps<P>;
+  constexpr int NB = blocks_of(P);
+  constexpr int ROWS = Tile::ROWS;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int nwaves = blockDim.x >> 6;
+  const LdsLayout L = lds_layout(P, pb, nwaves);
+  const unsigned char *s_q = smem + L.q;
+  const uint16_t *s_goff = reinterpret_cast<const uint16_t *>(smem + L.goff);
+  const T *s_oh = reinterpret_cast<const T *>(smem + L.oh);
+  const T *s_cz = reinterpret_cast<const T *>(smem + L.cz);
+  const T *s_coef = reinterpret_cast<const T *>(smem + L.coef);
+  const int16_t *s_succ = reinterpret_cast<const int16_t *>(smem + L.succ);
+
+  const int D = pb.D, S = pb.S, MT = pb.MT;
+  const int lane = threadIdx.x & 63;
+  // wave-uniform values live in scalar registers: the row-group loop and the buffer
+  // resources built from it stay scalar
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int r = lane & 15, q = lane >> 4;
+  const int ngroups = (n + ROWS - 1) / ROWS;
+  const int nload = (ROWS * D + 64 * Tile::NV - 1) / (64 * Tile::NV);
+  const int gstride = gridDim.x * nwaves;
+  int g = blockIdx.x * nwaves + wave;
+
+  // the first row group's loads go out before the tables are copied
+  Tile xt;
+  if (g < ngroups) xt.load(rows_rsrc(x, g * ROWS, n, D), nload, lane);
+  if (ROT) {
+    copy_to_lds(smem + L.q, pb.qfrag, L.q_bytes);
+    copy_to_lds(smem + L.goff, pb.goff, L.goff_bytes);
+  }
+  copy_to_lds(smem + L.oh, pb.oh, L.vec_bytes);
+  copy_to_lds(smem + L.cz, pb.cz, L.mp_bytes);
+  if (KT_::needs_coef) copy_to_lds(smem + L.coef, pb.coef, L.mp_bytes);
+  if (KT_::pairwise) copy_to_lds(smem + L.succ, pb.succ, L.succ_bytes);
+  T *Y = reinterpret_cast<T *>(smem + L.y + wave * L.slice_bytes);
+  // columns D..S-1 of every row are zero: the gather's padding slot and the unrotated read-out
+  for (int i = lane; i < ROWS * (S - D); i += 64) Y[(i / (S - D)) * S + D + i % (S - D)] = T(0);
+  __syncthreads();
+
+  const T scale = T(pb.scale);
+  const T prm = kind_param<KIND, T>(pb.Df, pb.kparam);
+  const unsigned char *Yb = reinterpret_cast<const unsigned char *>(Y + r * S);
+  const int bstride = kRowsPerBlock * S * static_cast<int>(sizeof(T));
+  const int4 *mtab = reinterpret_cast<const int4 *>(pb.mtab);
+
+  for (; g < ngroups; g += gstride) {
+    const int row0 = g * ROWS;
+    wave_sync();
+    xt.stage(nload, D, S, Y, s_oh, lane);
+    // the next row group's loads are in flight during everything below
+    const int gn = g + gstride;
+    if (gn < ngroups) xt.load(rows_rsrc(x, gn * ROWS, n, D), nload, lane);
+    wave_sync();
+
+    typename R::Frag bf[R::NTERM][NB][R::KTMAX];
+    if constexpr (ROT) {
+      gather_b<P>(bf, pb.KT, s_goff, Yb, bstride, q);
+      if constexpr (KT_::pairwise) wave_sync();  // the rows are overwritten with z below
+    }
+
+    Acc<T> a[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) a[b].init();
+
+    for (int m = 0; m < MT; ++m) {
+      T z[NB][4];
+      if constexpr (ROT) {
+        Acc4 acc[NB];
+        mtile<P>(acc, mtab[m], bf, s_q, lane);
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) z[b][e] = T(acc[b][e]) + s_cz[frag_pos<P, ROT>(m, q, e)];
+      } else {
+        T c4[4];
+        read4(c4, s_cz, 16 * m + 4 * q);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          T y4[4];
+          read4(y4, Y + (b * kRowsPerBlock + r) * S, 16 * m + 4 * q);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) z[b][e] = scale * y4[e] + c4[e];
+        }
+      }
+      if constexpr (KT_::pairwise) {
+        // z goes back to the rows (packed order); the terms need the successors, read below
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) Y[(b * kRowsPerBlock + r) * S + frag_pos<P, ROT>(m, q, e)] = z[b][e];
+      } else {
+        T cf[4] = {T(0), T(0), T(0), T(0)};
+        if constexpr (KT_::needs_coef) {
+          if constexpr (P == PATH_F64 && ROT) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) cf[e] = s_coef[frag_pos<P, ROT>(m, q, e)];
+          } else {
+            read4(cf, s_coef, 16 * m + 4 * q);
+          }
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          T v[3] = {T(0), T(0), T(0)};
+#pragma unroll
+          for (int e = 0; e < 4; ++e) phi<KIND, T>(v, a[b].p, z[b][e], T(0), cf[e], prm);
+#pragma unroll
+          for (int k = 0; k < KT_::nsum; ++k) a[b].add(k, v[k]);
+        }
+      }
+    }
+
+    if constexpr (KT_::pairwise) {
+      wave_sync();
+      for (int m = 0; m < MT; ++m) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const T *zr = Y + (b * kRowsPerBlock + r) * S;
+          T v[3] = {T(0), T(0), T(0)};
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int p = frag_pos<P, ROT>(m, q, e);
+            const int sp = s_succ[p];
+            T w[3] = {T(0), T(0), T(0)};
+            phi<KIND, T>(w, a[b].p, zr[p], zr[sp < 0 ? p : sp], T(0), prm);
+            v[0] += sp < 0 ? T(0) : w[0];
+          }
+          a[b].add(0, v[0]);
+        }
+      }
+    }
+
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      // combine the four lanes that hold the same row (lane, lane^16, lane^32, lane^48)
+#pragma unroll
+      for (int sh = 16; sh <= 32; sh <<= 1) {
+#pragma unroll
+        for (int k = 0; k < KT_::nsum; ++k) {
+          const T so = __shfl_xor(a[b].s[k], sh, 64);
+          const T co = __shfl_xor(a[b].c[k], sh, 64);
+          acc_merge(a[b], k, so, co);
+        }
+        if constexpr (KT_::has_product) a[b].p *= __shfl_xor(a[b].p, sh, 64);
+      }
+      const int row = row0 + b * kRowsPerBlock + r;
+      if (q == 0 && row < n) {
+        T s[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) s[k] = a[b].get(k) - T(pb.padc[k]);
+        out[row] = finalize<KIND, T>(s, a[b].p, pb.Df) + T(pb.bias);
+      }
+    }
+  }
 }
 
 // Kernel table of one path: index ((kind * 2) + rot) * 2 + vec.

@@ -11,8 +11,8 @@
 namespace curob {
 
 struct LdsLayout {
-  int q, o, olo, s, orig, coef, cz, succ, y;  // byte offsets
-  int q_bytes, vec_bytes, orig_bytes, mp_bytes, succ_bytes, y_bytes;
+  int q, goff, oh, cz, coef, succ, y;  // byte offsets
+  int q_bytes, goff_bytes, vec_bytes, mp_bytes, succ_bytes, slice_bytes;
   int fixed;  // bytes before the per-wave slices
   int total;
 };
@@ -22,38 +22,36 @@ __host__ __device__ inline int round16(int b) { return (b + 15) & ~15; }
 constexpr int kMaxLdsBytes = 160 * 1024;  // LDS per workgroup on gfx950
 constexpr int kMaxWavesPerWG = 8;
 
-// LDS carve of the resident kernel: rotation tiles, per-variable tables, per-position tables,
-// then one 16 x S slice per wave for the staged rows.
+// LDS carve of the resident kernel: rotation tiles, gather offsets, per-variable shift,
+// per-position tables, then one slice per wave holding its rows (16 per column block) plus one
+// spill row, S elements each.
 __host__ __device__ inline LdsLayout lds_layout(int path, const DevProb &pb, int nwaves) {
   const int esz = path == PATH_F64 ? 8 : 4;
   const int kw = kw_of(path);
+  const int rows = kRowsPerBlock * blocks_of(path);
   LdsLayout L;
   L.q_bytes = pb.rotated ? round16(pb.ntiles * 64 * (is_split(path) ? 16 * split_terms(path) : esz)) : 0;
-  L.orig_bytes = pb.rotated ? round16(pb.KT * kw * 2) : 0;
+  L.goff_bytes = pb.rotated ? round16(pb.KT * kw * 2) : 0;
   L.vec_bytes = round16(pb.D * esz);
   L.mp_bytes = round16(16 * pb.MT * esz);
   L.succ_bytes = round16(16 * pb.MT * 2);
-  L.y_bytes = kRowsPerWave * pb.S * esz;
+  L.slice_bytes = round16((rows + 1) * pb.S * esz);
   int off = 0;
   L.q = off;
   off += L.q_bytes;
-  L.orig = off;
-  off += L.orig_bytes;
-  L.o = off;
+  L.goff = off;
+  off += L.goff_bytes;
+  L.oh = off;
   off += L.vec_bytes;
-  L.olo = off;
-  off += path == PATH_F64 ? 0 : L.vec_bytes;
-  L.s = off;
-  off += L.vec_bytes;
-  L.coef = off;
-  off += L.mp_bytes;
   L.cz = off;
+  off += L.mp_bytes;
+  L.coef = off;
   off += L.mp_bytes;
   L.succ = off;
   off += L.succ_bytes;
   L.y = off;
   L.fixed = off;
-  off += round16(L.y_bytes) * nwaves;
+  off += L.slice_bytes * nwaves;
   L.total = off;
   return L;
 }

@@ -1,8 +1,8 @@
 // tables.cpp -- per-problem device tables for the resident evaluation kernel.
 //
-// Variables are renumbered into "packed" order: the three random groups of Sec. 1.2 (or the
-// hybrid groups of Sec. 5) one after another, so the rotation becomes block diagonal.  The
-// kernel multiplies by the packed matrix Qp tile by tile, skipping tiles that are all zero.
+// Variables are renumbered into "packed" order: the three random groups of Sec. 1.2 one after
+// another, so the rotation becomes block diagonal.  The kernel multiplies by the packed matrix
+// (pre-scaled by the function's s) tile by tile, skipping tiles that are all zero.
 #include "tables.h"
 
 #include <cmath>
@@ -33,8 +33,9 @@ float bf16_bits_to_float(uint16_t h) {
   return f;
 }
 
-int lds_stride(int D) {
-  int u = (D + 1 + 3) / 4;
+int lds_stride(int D, int m) {
+  const int need = D + 1 > m ? D + 1 : m;
+  int u = (need + 3) / 4;
   if ((u & 1) == 0) ++u;
   return 4 * u;
 }
@@ -51,8 +52,8 @@ size_t pad16(size_t b) { return (b + 15) & ~static_cast<size_t>(15); }
 }  // namespace
 
 bool build_host_tables(const Problem &p, int path, HostTables &ht, std::string &err) {
-  if (p.type == Problem::COMPOSITION) {
-    err = "composition problems are evaluated component by component";
+  if (p.type != Problem::BASIC) {
+    err = "hybrid and composition problems use the composite kernels";
     return false;
   }
   const int D = p.dim;
@@ -69,89 +70,99 @@ bool build_host_tables(const Problem &p, int path, HostTables &ht, std::string &
   const Segment &seg = p.segs[0];
   const int base = seg.base;
   const int kind = fn_spec(base).kind;
-  if (p.type == Problem::HYBRID) {
-    err = "hybrid problems use the segmented kernel";
-    return false;
-  }
+  const double s = seg.s, c = seg.c;
 
   ht = HostTables{};
   ht.path = path;
   auto store = [&](std::vector<unsigned char> &buf, size_t i, double v) {
     if (f64) put<double>(buf, i, v); else put<float>(buf, i, static_cast<float>(v));
   };
-  // per original variable: shift and scale
-  ht.o.assign(pad16(D * esz), 0);
-  ht.olo.assign(f64 ? 0 : pad16(D * esz), 0);
-  ht.sj.assign(pad16(D * esz), 0);
-  for (int j = 0; j < D; ++j) {
-    store(ht.o, j, p.o[j]);
-    if (!f64) put<float>(ht.olo, j, static_cast<float>(p.o[j] - static_cast<double>(static_cast<float>(p.o[j]))));
-    store(ht.sj, j, seg.s);
-  }
   // The sphere is rotation invariant (Sec. 3.1): |R y|^2 = |y|^2, so it is evaluated without
   // the rotation, in original variable order.
-  const bool rotate = p.rotated && !(base == 0 && seg.c == 0.0);
-  std::vector<int> order(D);
-  for (int pp = 0; pp < D; ++pp) order[pp] = rotate ? p.orig[pp] : pp;
-  // packed position -> original variable, padding -> D (a zero slot in LDS)
-  std::vector<int> slot(D);
-  ht.orig.assign(pad16(KT * KW * 2) / 2, static_cast<uint16_t>(D));
+  const bool rotate = p.rotated && !(base == 0 && c == 0.0);
+  std::vector<int> order(D), slot(D);
   for (int pp = 0; pp < D; ++pp) {
-    ht.orig[pp] = static_cast<uint16_t>(order[pp]);
+    order[pp] = rotate ? p.orig[pp] : pp;
     slot[order[pp]] = pp;
   }
-  // per packed position: coefficient, post-offset, formula successor
-  ht.coef.assign(pad16(Mp * esz), 0);
+  // shift: the path's rounding o_hi, and (FP32 paths) the remainder o_lo = o - o_hi
+  std::vector<double> olo(D, 0.0);
+  ht.oh.assign(pad16(D * esz), 0);
+  for (int j = 0; j < D; ++j) {
+    store(ht.oh, j, p.o[j]);
+    if (!f64) olo[j] = p.o[j] - static_cast<double>(static_cast<float>(p.o[j]));
+  }
+  // packed block-diagonal rotation, scaled by s
+  const int nb = static_cast<int>(p.Q.size());
+  auto qp = [&](int row, int col) -> double {
+    if (!rotate || row >= D || col >= D) return 0.0;
+    for (int k = 0; k < nb; ++k) {
+      const int off = p.blk_off[k], n = p.blk_n[k];
+      if (row >= off && row < off + n) {
+        if (col >= off && col < off + n) return s * p.Q[k][static_cast<size_t>(row - off) * n + (col - off)];
+        return 0.0;
+      }
+    }
+    return 0.0;
+  };
+  // gather: byte offset of each packed position's variable within an LDS row; padding reads
+  // the zero slot at column D
+  ht.goff.assign(pad16(KT * KW * 2) / 2, static_cast<uint16_t>(D * esz));
+  for (int pp = 0; pp < D; ++pp) ht.goff[pp] = static_cast<uint16_t>(order[pp] * esz);
+  // per packed position: c' = c - s (Q o_lo)_p, coefficient, formula successor.  Padding gets
+  // z = 0 (Schwefel: z = -420.97..., where g1 vanishes) and neutral coefficients.
   ht.cz.assign(pad16(Mp * esz), 0);
+  ht.coef.assign(pad16(Mp * esz), 0);
   ht.succ.assign(pad16(Mp * 2) / 2, static_cast<int16_t>(-1));
   const bool pair = kind_is_pairwise(kind), wraps = kind_pair_wraps(kind);
-  for (int pp = 0; pp < D; ++pp) {
+  for (int pp = 0; pp < Mp; ++pp) {
+    if (pp >= D) {
+      if (kind == K_SCHWEFEL) store(ht.cz, pp, -420.9687462275036);
+      if (kind == K_POWERS) store(ht.coef, pp, 2.0);
+      continue;
+    }
     const int i = order[pp];  // index the formula sees (original variable order)
+    double corr;
+    if (rotate) {
+      corr = 0.0;
+      for (int qq = 0; qq < D; ++qq) corr += qp(pp, qq) * olo[order[qq]];
+    } else {
+      corr = s * olo[i];
+    }
+    store(ht.cz, pp, c - corr);
     double cf = formula_coef(base, i, D);
     if (kind == K_GRIEWANK && !f64) cf /= 2.0 * M_PI;  // FP32 cosine takes revolutions
     store(ht.coef, pp, cf);
-    store(ht.cz, pp, seg.c);
     if (pair) {
-      int ni = i + 1 < D ? i + 1 : (wraps ? 0 : -1);
+      const int ni = i + 1 < D ? i + 1 : (wraps ? 0 : -1);
       ht.succ[pp] = static_cast<int16_t>(ni >= 0 ? slot[ni] : -1);
     }
   }
-  // nonzero tiles of the packed block-diagonal rotation
+  // nonzero tiles of s * Qp, m-tile by m-tile: the rows 16 m .. 16 m + 15 meet the blocks
+  // whose columns span a contiguous k-tile range
   int ntiles = 0;
-  ht.ktab.assign(4 * KT, 0);
+  ht.mtab.assign(4 * MT, 0);
   if (rotate) {
-    const int nb = static_cast<int>(p.Q.size());
-    auto qp = [&](int row, int col) -> double {
-      if (row >= D || col >= D) return 0.0;
-      for (int k = 0; k < nb; ++k) {
-        const int off = p.blk_off[k], n = p.blk_n[k];
-        if (row >= off && row < off + n) {
-          if (col >= off && col < off + n) return p.Q[k][static_cast<size_t>(row - off) * n + (col - off)];
-          return 0.0;
-        }
-      }
-      return 0.0;
-    };
     std::vector<std::pair<int, int>> tiles;  // (m, kt)
-    for (int kt = 0; kt < KT; ++kt) {
-      const int c0 = kt * KW, c1 = std::min(D, c0 + KW) - 1;
-      int mlo = 1 << 30, mhi = -1;
+    for (int m = 0; m < MT; ++m) {
+      const int r0 = 16 * m, r1 = std::min(D, r0 + 16) - 1;
+      int klo = 1 << 30, khi = -1;
       for (int k = 0; k < nb; ++k) {
         const int off = p.blk_off[k], n = p.blk_n[k];
-        if (off <= c1 && off + n - 1 >= c0) {
-          mlo = std::min(mlo, off / 16);
-          mhi = std::max(mhi, (off + n - 1) / 16);
+        if (off <= r1 && off + n - 1 >= r0) {
+          klo = std::min(klo, off / KW);
+          khi = std::max(khi, (off + n - 1) / KW);
         }
       }
-      ht.ktab[4 * kt + 0] = mlo;
-      ht.ktab[4 * kt + 1] = mhi;
-      ht.ktab[4 * kt + 2] = static_cast<int>(tiles.size());
-      for (int m = mlo; m <= mhi; ++m) tiles.emplace_back(m, kt);
+      ht.mtab[4 * m + 0] = klo;
+      ht.mtab[4 * m + 1] = khi;
+      ht.mtab[4 * m + 2] = static_cast<int>(tiles.size());
+      for (int kt = klo; kt <= khi; ++kt) tiles.emplace_back(m, kt);
     }
     ntiles = static_cast<int>(tiles.size());
     if (is_split(path)) {
       // tile t: nterm fragments [64 lanes][8] (hi, [mid,] lo); lane l holds
-      // A[i = l % 16][k = 8 (l / 16) + e] = Qp[16 m + i][32 kt + k], split into bf16 terms
+      // A[i = l % 16][k = 8 (l / 16) + e] = s Qp[16 m + i][32 kt + k], split into bf16 terms
       const int nterm = split_terms(path);
       ht.qfrag.assign(static_cast<size_t>(ntiles) * nterm * 64 * 8 * 2, 0);
       uint16_t *qb = reinterpret_cast<uint16_t *>(ht.qfrag.data());
@@ -168,7 +179,7 @@ bool build_host_tables(const Problem &p, int path, HostTables &ht, std::string &
           }
       }
     } else {
-      // tile t: [64 lanes], lane l holds A[i = l % 16][k = l / 16] = Qp[16 m + i][4 kt + k]
+      // tile t: [64 lanes], lane l holds A[i = l % 16][k = l / 16] = s Qp[16 m + i][4 kt + k]
       ht.qfrag.assign(pad16(static_cast<size_t>(ntiles) * 64 * esz), 0);
       for (int t = 0; t < ntiles; ++t) {
         const int m = tiles[t].first, kt = tiles[t].second;
@@ -179,7 +190,7 @@ bool build_host_tables(const Problem &p, int path, HostTables &ht, std::string &
 
   DevProb &pb = ht.pb;
   pb.D = D;
-  pb.S = lds_stride(D);
+  pb.S = lds_stride(D, Mp);
   pb.KT = KT;
   pb.MT = MT;
   pb.ntiles = ntiles;
@@ -188,6 +199,17 @@ bool build_host_tables(const Problem &p, int path, HostTables &ht, std::string &
   pb.Df = D;
   pb.bias = p.fopt;
   pb.kparam = 10.0 / std::pow(static_cast<double>(D), 1.2);
+  pb.scale = s;
+  // what the padded positions (z = 0, or w = 0 for Schwefel) add to each sum
+  const double npad = static_cast<double>(Mp - D);
+  pb.padc[0] = pb.padc[1] = pb.padc[2] = 0.0;
+  if (kind == K_WEIERSTRASS) pb.padc[0] = -npad * (2.0 - 9.5367431640625e-07);  // sum_k a^k cos(pi 3^k)
+  if (kind == K_ACKLEY) pb.padc[1] = npad;                                          // cos(0) = 1
+  if (kind == K_LUNACEK) {
+    pb.padc[0] = 6.25 * npad;  // (0 - 2.5)^2
+    pb.padc[1] = 6.25 * npad;  // (0 + 2.5)^2
+    pb.padc[2] = -npad;        // cos(2 pi (0 - 2.5)) = -1
+  }
   return true;
 }
 
@@ -208,15 +230,13 @@ hipError_t upload_tables(const HostTables &ht, DevTables &dt) {
   };
   DevProb pb = ht.pb;
   hipError_t e;
-  if ((e = up(ht.o.data(), ht.o.size(), &pb.o)) != hipSuccess) return e;
-  if ((e = up(ht.olo.data(), ht.olo.size(), &pb.olo)) != hipSuccess) return e;
-  if ((e = up(ht.sj.data(), ht.sj.size(), &pb.sj)) != hipSuccess) return e;
-  if ((e = up(ht.orig.data(), ht.orig.size() * 2, reinterpret_cast<const void **>(&pb.orig))) != hipSuccess) return e;
-  if ((e = up(ht.coef.data(), ht.coef.size(), &pb.coef)) != hipSuccess) return e;
+  if ((e = up(ht.oh.data(), ht.oh.size(), &pb.oh)) != hipSuccess) return e;
+  if ((e = up(ht.goff.data(), ht.goff.size() * 2, reinterpret_cast<const void **>(&pb.goff))) != hipSuccess) return e;
   if ((e = up(ht.cz.data(), ht.cz.size(), &pb.cz)) != hipSuccess) return e;
+  if ((e = up(ht.coef.data(), ht.coef.size(), &pb.coef)) != hipSuccess) return e;
   if ((e = up(ht.succ.data(), ht.succ.size() * 2, reinterpret_cast<const void **>(&pb.succ))) != hipSuccess) return e;
   if ((e = up(ht.qfrag.data(), ht.qfrag.size(), &pb.qfrag)) != hipSuccess) return e;
-  if ((e = up(ht.ktab.data(), ht.ktab.size() * 4, reinterpret_cast<const void **>(&pb.ktab))) != hipSuccess) return e;
+  if ((e = up(ht.mtab.data(), ht.mtab.size() * 4, reinterpret_cast<const void **>(&pb.mtab))) != hipSuccess) return e;
   dt.pb = pb;
   dt.ready = true;
   return hipSuccess;

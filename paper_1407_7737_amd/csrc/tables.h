@@ -22,10 +22,10 @@ struct DevTables {
 // Host-side images of the tables (exposed for CPU checks of the layout).
 struct HostTables {
   int path = 0;
-  std::vector<unsigned char> o, olo, sj, coef, cz, qfrag;
-  std::vector<uint16_t> orig;
+  std::vector<unsigned char> oh, cz, coef, qfrag;
+  std::vector<uint16_t> goff;
   std::vector<int16_t> succ;
-  std::vector<int> ktab;
+  std::vector<int> mtab;
   DevProb pb{};
 };
 
@@ -40,7 +40,8 @@ hipError_t upload_tables(const HostTables &ht, DevTables &dt);
 uint16_t bf16_bits_rne(float f);
 float bf16_bits_to_float(uint16_t h);
 
-// LDS row stride: the smallest 4u >= D + 1 with u odd (16 rows then fall in distinct banks).
-int lds_stride(int D);
+// LDS row stride: the smallest 4u >= max(D + 1, m) with u odd (16 rows then fall in distinct
+// banks), m the padded position count.
+int lds_stride(int D, int m);
 
 }  // namespace curob
