@@ -126,24 +126,51 @@ int curob_get_problem(int fid, double *o, double *R);
  * ..., seed) produces for basic function `fid` (0..22). */
 int curob_generate_basic(int fid, int dim, unsigned long long seed, double *o, double *R);
 
-/* ---- batched populations (one launch, replayed as a HIP graph) -------------------------- */
+/* ---- batched populations (one persistent launch, replayed as a HIP graph) --------------- */
 
 typedef struct curob_batch curob_batch;
 
-/* Plans k populations evaluated by one persistent launch: population i has counts[i] rows of
- * dims[i] (2..128) elements and function fids[i] (0..22), each with its own o and R drawn from
- * (seed, i).  The plan, device tables and a captured HIP graph are owned by *out. */
+/* Plans k populations evaluated by one persistent launch (needs an initialised library; the
+ * launches go to the library stream).  Population i has counts[i] >= 0 rows of dims[i]
+ * (2..128) FP32 elements and is Tab. 1 function fids[i] (0..22) with that function's
+ * transform (Secs. 3-4), its shift and rotation drawn like a custom problem with id
+ * 2048 + i (the key (2048 + i) << 8 of the generator streams, Sec. 1.2) at dimension dims[i].
+ * Arithmetic: the FP32 split path, three or six BF16 products per formula as the default mode
+ * picks.  The plan, device tables and the HIP graph are owned by *out; the default launch
+ * shape is two waves per workgroup, two row groups per item, two workgroups per CU.
+ * Errors: CUROB_E_STATE before initialize, CUROB_E_FID for a fid outside 0..22, CUROB_E_ARG for
+ * k outside 1..65536, a dimension outside 2..128 or a negative count, CUROB_E_HIP. */
 int curob_batch_create(int k, const int *fids, const int *dims, const int *counts,
                        unsigned long long seed, curob_batch **out);
 
-/* Points the batch at device buffers: d_xs[i] holds counts[i] x dims[i] floats, d_outs[i]
- * receives counts[i] floats.  Arrays of k host-side entries. */
+/* Points the batch at device buffers: d_xs[i] holds counts[i] x dims[i] floats (row-major),
+ * d_outs[i] receives counts[i] floats; host arrays of k device pointers (may be NULL where
+ * counts[i] = 0).  Waits for the library stream, then copies the pointer tables to the
+ * device; the first bind captures the graph, later binds reuse it. */
 int curob_batch_bind(curob_batch *b, const float *const *d_xs, float *const *d_outs);
 
-/* Replays the captured graph on the library stream (asynchronous). */
+/* Replays the captured graph on the library stream (asynchronous).  CUROB_E_STATE before the
+ * first bind. */
 int curob_batch_run(curob_batch *b);
 
-/* Frees a batch.  NULL is ignored. */
+/* The same launch without the graph (for timing the graph's benefit). */
+int curob_batch_run_direct(curob_batch *b);
+
+/* Sets the launch shape: waves per workgroup (1..4, and the LDS of the largest population
+ * must fit), row groups of 32 rows per work item, workgroups (clamped to the item count).
+ * Re-plans the schedule and re-captures the graph. */
+int curob_batch_configure(curob_batch *b, int waves, int groups_per_item, int grid);
+
+/* The current launch shape and the number of work items. */
+int curob_batch_shape(const curob_batch *b, int *waves, int *groups_per_item, int *grid, int *nitems);
+
+/* Autotuner: times every candidate shape (waves {1,2,4} x groups per item {1,2,4,8} x waves x
+ * workgroups {CUs/2, CUs, 2 CUs, 4 CUs}) with `reps` launches each on the bound buffers,
+ * keeps the fastest and re-captures the graph; *best_us receives its time per launch.
+ * Needs a bound batch (CUROB_E_STATE otherwise). */
+int curob_batch_tune(curob_batch *b, int reps, float *best_us);
+
+/* Frees a batch (after waiting for the library stream).  NULL is ignored. */
 int curob_batch_destroy(curob_batch *b);
 
 #ifdef __cplusplus

@@ -8,6 +8,7 @@ tensors provide device memory and the stream; all evaluation happens in the HIP 
 from __future__ import annotations
 
 import ctypes
+import os
 
 import numpy as np
 
@@ -158,7 +159,8 @@ def generate_basic(fid: int, dim: int, seed: int):
 
 class Batch:
     """Populations of uneven size, dimension and function evaluated by one persistent launch
-    replayed as a HIP graph (curob_batch_*)."""
+    replayed as a HIP graph (curob_batch_*).  Population i is Tab. 1 function fids[i] at
+    dimension dims[i] with counts[i] rows, its random data keyed like custom id 2048 + i."""
 
     def __init__(self, fids, dims, counts, seed: int = 0):
         self.k = len(fids)
@@ -168,16 +170,81 @@ class Batch:
         check(lib.curob_batch_create(self.k, *[a.ctypes.data_as(ip) for a in arr], int(seed), ctypes.byref(h)))
         self._h = h
         self.fids, self.dims, self.counts = (a.copy() for a in arr)
+        self.seed = int(seed)
 
     def bind(self, xs, outs) -> None:
-        X = (ctypes.c_void_p * self.k)(*[_ptr(t) for t in xs])
-        O = (ctypes.c_void_p * self.k)(*[_ptr(t) for t in outs])
+        """xs[i]: (counts[i], dims[i]) float32 CUDA tensor; outs[i]: (counts[i],) float32."""
+        import torch
+        if len(xs) != self.k or len(outs) != self.k:
+            raise ValueError("one input and one output buffer per population")
+        for i, (x, o) in enumerate(zip(xs, outs)):
+            if self.counts[i] == 0:
+                continue
+            if x.dtype != torch.float32 or o.dtype != torch.float32 or not x.is_cuda or not o.is_cuda:
+                raise TypeError("batch buffers are float32 CUDA tensors")
+            if tuple(x.shape) != (int(self.counts[i]), int(self.dims[i])) or not x.is_contiguous():
+                raise ValueError(f"population {i}: expected a contiguous ({self.counts[i]}, {self.dims[i]}) input")
+            if o.numel() < self.counts[i] or not o.is_contiguous():
+                raise ValueError(f"population {i}: output needs {self.counts[i]} contiguous entries")
+        X = (ctypes.c_void_p * self.k)(*[_ptr(t) if t is not None and t.numel() else None for t in xs])
+        O = (ctypes.c_void_p * self.k)(*[_ptr(t) if t is not None and t.numel() else None for t in outs])
         self._keep = (xs, outs)
+        check(lib.curob_set_stream(_torch_stream()))
         check(lib.curob_batch_bind(self._h, X, O))
 
     def run(self) -> None:
+        """Replays the captured graph on torch's current stream."""
         check(lib.curob_set_stream(_torch_stream()))
         check(lib.curob_batch_run(self._h))
+
+    def run_direct(self) -> None:
+        """The same persistent launch without the graph."""
+        check(lib.curob_set_stream(_torch_stream()))
+        check(lib.curob_batch_run_direct(self._h))
+
+    def configure(self, waves: int, groups_per_item: int, grid: int) -> None:
+        check(lib.curob_batch_configure(self._h, int(waves), int(groups_per_item), int(grid)))
+
+    def shape(self) -> dict:
+        v = [ctypes.c_int() for _ in range(4)]
+        check(lib.curob_batch_shape(self._h, *[ctypes.byref(a) for a in v]))
+        return dict(zip(("waves", "groups_per_item", "grid", "items"), (a.value for a in v)))
+
+    def signature(self) -> str:
+        import hashlib
+
+        import torch
+        h = hashlib.sha256()
+        for a in (self.fids, self.dims, self.counts):
+            h.update(a.tobytes())
+        h.update(torch.cuda.get_device_name().encode())
+        return h.hexdigest()[:24]
+
+    def tune(self, reps: int = 20, cache: str | None = None) -> dict:
+        """Autotunes the launch shape on the bound buffers (curob_batch_tune).  With a cache
+        path (JSON), a shape stored for the same populations and device is applied without
+        timing, and a freshly tuned one is stored."""
+        import json
+        key = self.signature()
+        entries = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                entries = json.load(f)
+            if key in entries:
+                e = entries[key]
+                self.configure(e["waves"], e["groups_per_item"], e["grid"])
+                return dict(self.shape(), us=e.get("us"), cached=True)
+        check(lib.curob_set_stream(_torch_stream()))
+        best = ctypes.c_float()
+        check(lib.curob_batch_tune(self._h, int(reps), ctypes.byref(best)))
+        res = dict(self.shape(), us=float(best.value), cached=False)
+        if cache:
+            entries[key] = {k: res[k] for k in ("waves", "groups_per_item", "grid", "us")}
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(entries, f, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return res
 
     def close(self) -> None:
         if getattr(self, "_h", None):

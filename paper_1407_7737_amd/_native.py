@@ -29,8 +29,10 @@ EXPORTED = [
     "initialize", "dispose", "func_evaluate", "func_evaluatef", "h_func_evaluate", "h_func_evaluatef",
     "curob_set_stream", "curob_set_mode", "curob_define_basic", "curob_define_hybrid",
     "curob_define_composition", "curob_last_error", "curob_get_problem", "curob_generate_basic",
-    "curob_batch_create", "curob_batch_bind", "curob_batch_run", "curob_batch_destroy",
+    "curob_batch_create", "curob_batch_bind", "curob_batch_run", "curob_batch_run_direct",
+    "curob_batch_configure", "curob_batch_shape", "curob_batch_tune", "curob_batch_destroy",
 ]
+BATCH_KEY_BASE = 2048  # population i of a batch keys its random data like custom id 2048 + i
 
 
 class CurobError(RuntimeError):
@@ -41,7 +43,7 @@ class CurobError(RuntimeError):
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is not built; run python -m paper_1407_7737_amd.build")
+        raise ImportError(f"{LIB_PATH} is not built; run python paper_1407_7737_amd/build.py")
     L = ctypes.CDLL(LIB_PATH)
     i32, u64, vp = ctypes.c_int, ctypes.c_ulonglong, ctypes.c_void_p
     dp, ip = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
@@ -63,6 +65,10 @@ def _load():
         "curob_batch_create": (i32, [i32, ip, ip, ip, u64, ctypes.POINTER(vp)]),
         "curob_batch_bind": (i32, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp)]),
         "curob_batch_run": (i32, [vp]),
+        "curob_batch_run_direct": (i32, [vp]),
+        "curob_batch_configure": (i32, [vp, i32, i32, i32]),
+        "curob_batch_shape": (i32, [vp, ip, ip, ip, ip]),
+        "curob_batch_tune": (i32, [vp, i32, ctypes.POINTER(ctypes.c_float)]),
         "curob_batch_destroy": (i32, [vp]),
     }
     for name, (res, args) in sig.items():

@@ -1,6 +1,6 @@
 """Builds libcurob.so (HIP for gfx950) in-tree.
 
-    python -m paper_1407_7737_amd.build
+    python paper_1407_7737_amd/build.py
 
 Every HIP/C++ source under csrc/ is compiled with hipcc for gfx950 only, then linked into
 paper_1407_7737_amd/libcurob.so next to this file.  Packed FP32 instructions are disabled

@@ -40,6 +40,7 @@ struct Context {
   int mode = CUROB_MODE_SPLIT;
   hipStream_t stream = nullptr;
   std::map<int, std::unique_ptr<Entry>> entries;
+  CompositeScratch scratch;   // tiled partial sums, pairwise z, composition components
   void *stage_x = nullptr;    // maxc * dim doubles, for the h_ wrappers
   void *stage_out = nullptr;  // maxc doubles
 };
@@ -63,13 +64,15 @@ int hip_fail(hipError_t e, const char *what) {
 
 void free_context() {
   g_ctx.entries.clear();
+  g_ctx.scratch.release();
   if (g_ctx.stage_x) (void)hipFree(g_ctx.stage_x);
   if (g_ctx.stage_out) (void)hipFree(g_ctx.stage_out);
   g_ctx = Context{};
 }
 
-// Builds device data for a problem on every path; basic problems get the resident tables,
-// hybrids and compositions the segmented / composite tables.
+// Builds device data for a problem on every path: basic problems within the resident kernel's
+// dimension range get its tables, everything else the tiled / composition tables, and the
+// context's scratch grows to what the problem needs.
 int prepare_entry(Entry &e) {
   const Problem &p = e.host;
   if (p.type == Problem::BASIC) {
@@ -83,8 +86,16 @@ int prepare_entry(Entry &e) {
       }
     }
   }
-  hipError_t he = build_composite(p, e.comp);
-  if (he != hipSuccess) return hip_fail(he, "uploading composite tables");
+  std::string err;
+  hipError_t he = build_composite(p, e.comp, err);
+  if (he != hipSuccess) {
+    if (!err.empty()) return fail(CUROB_E_ARG, "%s", err.c_str());
+    return hip_fail(he, "uploading composite tables");
+  }
+  size_t pb = 0, zb = 0, gb = 0;
+  composite_scratch_needs(e.comp, pb, zb, gb);
+  he = g_ctx.scratch.reserve(pb, zb, gb);
+  if (he != hipSuccess) return hip_fail(he, "allocating scratch");
   return CUROB_OK;
 }
 
@@ -106,8 +117,11 @@ int fp32_path(int fid) {
     default: break;
   }
   auto it = g_ctx.entries.find(fid);
-  if (it == g_ctx.entries.end() || it->second->host.segs.empty()) return PATH_SPLIT;
-  return needs_six_products(it->second->host.segs[0].base) ? PATH_SPLIT6 : PATH_SPLIT;
+  if (it == g_ctx.entries.end()) return PATH_SPLIT;
+  const Problem &p = it->second->host;
+  // compositions choose per component inside launch_composite
+  if (p.type == Problem::COMPOSITION) return PATH_SPLIT;
+  return problem_needs_six(p) ? PATH_SPLIT6 : PATH_SPLIT;
 }
 
 int check_ready() {
@@ -135,8 +149,11 @@ int evaluate(int path, int fid, const void *x, int n, void *out) {
   if (e->host.type == Problem::BASIC && e->dev[path].ready) {
     const DevProb &pb = e->dev[path].pb;
     he = launch_resident(path, pb, x, out, n, resident_shape(path, pb, n, g_ctx.num_cu), g_ctx.stream);
+  } else if (e->comp.ready) {
+    const bool split_auto = g_ctx.mode == CUROB_MODE_SPLIT && path != PATH_F64;
+    he = launch_composite(path, split_auto, e->comp, x, out, n, g_ctx.num_cu, g_ctx.scratch, g_ctx.stream);
   } else {
-    he = launch_composite(path, e->comp, x, out, n, g_ctx.num_cu, g_ctx.stream);
+    return fail(CUROB_E_HIP, "function id %d has no device tables", fid);
   }
   if (he != hipSuccess) return hip_fail(he, "kernel launch");
   return CUROB_OK;
@@ -162,6 +179,7 @@ int h_evaluate(int path, int fid, const T *hx, int n, T *hout) {
 }  // namespace
 
 int context_num_cu() { return g_ctx.num_cu; }
+bool context_ready() { return g_ctx.ready; }
 hipStream_t context_stream() { return g_ctx.stream; }
 int set_error(int code, const std::string &msg) { return fail(code, "%s", msg.c_str()); }
 

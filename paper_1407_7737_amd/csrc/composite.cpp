@@ -1,21 +1,195 @@
-// composite.cpp -- host side of the hybrid / composition / large-dimension paths.
+// composite.cpp -- host side of the tiled path (large-dimension basic functions, hybrids) and
+// of compositions.
 #include "composite.h"
+
+#include <algorithm>
+
+#include "kernels.h"
 
 namespace curob {
 
+hipError_t launch_tiled_split(int, const TiledProb &, const void *, void *, int, void *, void *, hipStream_t);
+hipError_t launch_tiled_split6(int, const TiledProb &, const void *, void *, int, void *, void *, hipStream_t);
+hipError_t launch_tiled_f32(int, const TiledProb &, const void *, void *, int, void *, void *, hipStream_t);
+hipError_t launch_tiled_f64(int, const TiledProb &, const void *, void *, int, void *, void *, hipStream_t);
+hipError_t launch_blend(bool f64, const void *x, int n, int D, int nc, const double *o, const double *sigma,
+                        const double *lambda, const double *bias, const void *G, int gstride, double fopt, void *out,
+                        hipStream_t st);
+
+hipError_t launch_tiled(int path, int kind_hint, const TiledProb &tp, const void *x, void *out, int n, void *partials,
+                        void *zbuf, hipStream_t st) {
+  switch (path) {
+    case PATH_SPLIT: return launch_tiled_split(kind_hint, tp, x, out, n, partials, zbuf, st);
+    case PATH_SPLIT6: return launch_tiled_split6(kind_hint, tp, x, out, n, partials, zbuf, st);
+    case PATH_F32: return launch_tiled_f32(kind_hint, tp, x, out, n, partials, zbuf, st);
+    case PATH_F64: return launch_tiled_f64(kind_hint, tp, x, out, n, partials, zbuf, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 void CompositeDev::release() {
+  for (auto &t : tiled) t.release();
+  for (auto &c : comps) {
+    for (auto &t : c.tiled) t.release();
+    for (auto &r : c.res) r.release();
+  }
+  comps.clear();
   for (void *p : allocs) (void)hipFree(p);
   allocs.clear();
   ready = false;
 }
 
-hipError_t build_composite(const Problem &, CompositeDev &cd) {
-  cd.ready = false;
+hipError_t CompositeScratch::reserve(size_t pb, size_t zb, size_t gb) {
+  auto grow = [](void *&ptr, size_t &have, size_t want) -> hipError_t {
+    if (want <= have) return hipSuccess;
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    have = 0;
+    hipError_t e = hipMalloc(&ptr, want);
+    if (e == hipSuccess) have = want;
+    return e;
+  };
+  hipError_t e = grow(partials, partials_bytes, pb);
+  if (e == hipSuccess) e = grow(zbuf, zbuf_bytes, zb);
+  if (e == hipSuccess) e = grow(gbuf, gbuf_bytes, gb);
+  return e;
+}
+
+void CompositeScratch::release() {
+  if (partials) (void)hipFree(partials);
+  if (zbuf) (void)hipFree(zbuf);
+  if (gbuf) (void)hipFree(gbuf);
+  *this = CompositeScratch{};
+}
+
+namespace {
+
+bool fits_resident(const Problem &p) { return p.type == Problem::BASIC && p.dim <= 16 * kMaxMT; }
+
+hipError_t build_basic_or_hybrid(const Problem &p, TiledDev (&tiled)[PATH_COUNT], std::string &err) {
+  for (int path = 0; path < PATH_COUNT; ++path) {
+    hipError_t e = build_tiled(p, path, tiled[path], err);
+    if (e != hipSuccess) return e;
+  }
   return hipSuccess;
 }
 
-hipError_t launch_composite(int, const CompositeDev &cd, const void *, void *, int, int, hipStream_t) {
+}  // namespace
+
+hipError_t build_composite(const Problem &p, CompositeDev &cd, std::string &err) {
+  cd.release();
+  cd.dim = p.dim;
+  cd.fopt = p.fopt;
+  if (p.type == Problem::BASIC) {
+    if (fits_resident(p)) return hipSuccess;  // the resident kernel covers it
+    cd.kind_hint = fn_spec(p.segs[0].base).kind;
+    hipError_t e = build_basic_or_hybrid(p, cd.tiled, err);
+    if (e == hipSuccess) cd.ready = true;
+    return e;
+  }
+  if (p.type == Problem::HYBRID) {
+    cd.kind_hint = -1;
+    hipError_t e = build_basic_or_hybrid(p, cd.tiled, err);
+    if (e == hipSuccess) cd.ready = true;
+    return e;
+  }
+  // composition: components with f_opt 0 (G_i excludes it), FP64 blend tables
+  cd.is_composition = true;
+  const int nc = static_cast<int>(p.comps.size());
+  if (nc < 1 || nc > 8) {
+    err = "compositions take 1..8 components";
+    return hipErrorInvalidValue;
+  }
+  cd.comps.resize(nc);
+  std::vector<double> o(static_cast<size_t>(nc) * p.dim);
+  for (int i = 0; i < nc; ++i) {
+    Problem c = p.comps[i];
+    c.fopt = 0.0;
+    std::copy(c.o.begin(), c.o.end(), o.begin() + static_cast<size_t>(i) * p.dim);
+    CompositeDev::Component &cc = cd.comps[i];
+    cc.six = problem_needs_six(c);
+    if (fits_resident(c)) {
+      cc.resident = true;
+      for (int path = 0; path < PATH_COUNT; ++path) {
+        HostTables ht;
+        if (!build_host_tables(c, path, ht, err)) return hipErrorInvalidValue;
+        hipError_t e = upload_tables(ht, cc.res[path]);
+        if (e != hipSuccess) return e;
+      }
+    } else {
+      hipError_t e = build_basic_or_hybrid(c, cc.tiled, err);
+      if (e != hipSuccess) return e;
+    }
+  }
+  auto up = [&](const std::vector<double> &v, const double **dst) -> hipError_t {
+    void *d = nullptr;
+    hipError_t e = hipMalloc(&d, v.size() * sizeof(double));
+    if (e != hipSuccess) return e;
+    cd.allocs.push_back(d);
+    *dst = static_cast<const double *>(d);
+    return hipMemcpy(d, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice);
+  };
+  hipError_t e;
+  if ((e = up(o, &cd.o64)) != hipSuccess) return e;
+  if ((e = up(p.sigma, &cd.sig)) != hipSuccess) return e;
+  if ((e = up(p.lambda, &cd.lam)) != hipSuccess) return e;
+  if ((e = up(p.cbias, &cd.cb)) != hipSuccess) return e;
+  cd.ready = true;
+  return hipSuccess;
+}
+
+void composite_scratch_needs(const CompositeDev &cd, size_t &pb, size_t &zb, size_t &gb) {
+  pb = zb = gb = 0;
+  auto acc_tiled = [&](const TiledDev (&t)[PATH_COUNT]) {
+    for (int path = 0; path < PATH_COUNT; ++path)
+      if (t[path].ready) {
+        pb = std::max(pb, tiled_partials_bytes(t[path].tp, path));
+        zb = std::max(zb, tiled_z_bytes(t[path].tp, path));
+      }
+  };
+  if (!cd.ready) return;
+  if (!cd.is_composition) {
+    acc_tiled(cd.tiled);
+    return;
+  }
+  for (const auto &c : cd.comps)
+    if (!c.resident) acc_tiled(c.tiled);
+  gb = static_cast<size_t>(cd.comps.size()) * kChunkRows * sizeof(double);
+}
+
+hipError_t launch_composite(int path, bool split_auto, const CompositeDev &cd, const void *x, void *out, int n,
+                            int num_cu, CompositeScratch &sc, hipStream_t st) {
   if (!cd.ready) return hipErrorNotSupported;
+  const size_t esz = path == PATH_F64 ? 8 : 4;
+  for (int c0 = 0; c0 < n; c0 += kChunkRows) {
+    const int ch = std::min(kChunkRows, n - c0);
+    const unsigned char *xc = static_cast<const unsigned char *>(x) + static_cast<size_t>(c0) * cd.dim * esz;
+    unsigned char *oc = static_cast<unsigned char *>(out) + static_cast<size_t>(c0) * esz;
+    hipError_t e;
+    if (!cd.is_composition) {
+      e = launch_tiled(path, cd.kind_hint, cd.tiled[path].tp, xc, oc, ch, sc.partials, sc.zbuf, st);
+      if (e != hipSuccess) return e;
+      continue;
+    }
+    const int nc = static_cast<int>(cd.comps.size());
+    for (int i = 0; i < nc; ++i) {
+      const CompositeDev::Component &cc = cd.comps[i];
+      int cp = path;
+      if (split_auto && is_split(path)) cp = cc.six ? PATH_SPLIT6 : PATH_SPLIT;
+      unsigned char *gi = static_cast<unsigned char *>(sc.gbuf) + static_cast<size_t>(i) * kChunkRows * esz;
+      if (cc.resident) {
+        const DevProb &pb = cc.res[cp].pb;
+        e = launch_resident(cp, pb, xc, gi, ch, resident_shape(cp, pb, ch, num_cu), st);
+      } else {
+        const int hint = cc.tiled[cp].tp.nsegs == 1 ? cc.tiled[cp].tp.segs[0].kind : -1;
+        e = launch_tiled(cp, hint, cc.tiled[cp].tp, xc, gi, ch, sc.partials, sc.zbuf, st);
+      }
+      if (e != hipSuccess) return e;
+    }
+    e = launch_blend(path == PATH_F64, xc, ch, cd.dim, nc, cd.o64, cd.sig, cd.lam, cd.cb, sc.gbuf, kChunkRows, cd.fopt,
+                     oc, st);
+    if (e != hipSuccess) return e;
+  }
   return hipSuccess;
 }
 

@@ -1,26 +1,59 @@
-// composite.h -- hybrid (Sec. 5) and composition (Sec. 6) evaluation, and basic functions of
-// dimension above the resident kernel's range.
+// composite.h -- everything the resident kernel does not cover: basic functions above its
+// dimension range and hybrids (the tiled path), and compositions (Sec. 6), whose components are
+// evaluated by the resident or tiled path and blended with FP64 weights.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
+#include <string>
 #include <vector>
 
 #include "problem.h"
+#include "tables.h"
+#include "tiled.h"
 
 namespace curob {
 
 struct CompositeDev {
-  std::vector<void *> allocs;
+  struct Component {
+    TiledDev tiled[PATH_COUNT];
+    DevTables res[PATH_COUNT];
+    bool resident = false;
+    bool six = false;  // split mode: six products
+  };
   bool ready = false;
+  bool is_composition = false;
+  int dim = 0;
+  TiledDev tiled[PATH_COUNT];  // basic (large dimension) or hybrid
+  int kind_hint = -1;          // formula family for a basic problem, -1 for hybrids
+  std::vector<Component> comps;
+  std::vector<void *> allocs;  // blend tables
+  const double *o64 = nullptr; // component optima, ncomp x dim
+  const double *sig = nullptr, *lam = nullptr, *cb = nullptr;
+  double fopt = 100.0;
   void release();
 };
 
-// Uploads whatever the composite kernels need for p (nothing for small basic problems).
-hipError_t build_composite(const Problem &p, CompositeDev &cd);
+// Scratch shared by all composite evaluations of a context (one chunk of rows).
+struct CompositeScratch {
+  void *partials = nullptr;
+  void *zbuf = nullptr;
+  void *gbuf = nullptr;
+  size_t partials_bytes = 0, zbuf_bytes = 0, gbuf_bytes = 0;
+  hipError_t reserve(size_t pb, size_t zb, size_t gb);
+  void release();
+};
 
-// Evaluates n rows of x into out on the given path.
-hipError_t launch_composite(int path, const CompositeDev &cd, const void *x, void *out, int n, int num_cu,
-                            hipStream_t st);
+// Uploads whatever the composite kernels need for p.  Basic problems within the resident
+// kernel's range need nothing here.
+hipError_t build_composite(const Problem &p, CompositeDev &cd, std::string &err);
+
+// Scratch sizes the problem needs.
+void composite_scratch_needs(const CompositeDev &cd, size_t &pb, size_t &zb, size_t &gb);
+
+// Evaluates n rows of x into out.  path is the arithmetic of the call; in split mode
+// (split_auto) the components of a composition pick three or six products per formula.
+hipError_t launch_composite(int path, bool split_auto, const CompositeDev &cd, const void *x, void *out, int n,
+                            int num_cu, CompositeScratch &sc, hipStream_t st);
 
 }  // namespace curob

@@ -277,9 +277,13 @@ __device__ __forceinline__ void read4(T (&v)[4], const T *row, int p0) {
   }
 }
 
+// Evaluates row groups g, g + gstride, ... < gend of one problem with the calling wave
+// (the workgroup's waves share the problem's LDS tables).  setup: copy the tables and clear
+// the slices' padding columns first (every wave of the workgroup must take part).
 template <int P, int KIND, int ROT, int VEC>
-__global__ __launch_bounds__(512) void k_eval_resident(DevProb pb, const typename PathT<P>::T *__restrict__ x,
-                                                       typename PathT<P>::T *__restrict__ out, int n) {
+__device__ __forceinline__ void resident_eval(const DevProb &pb, const typename PathT<P>::T *__restrict__ x,
+                                              typename PathT<P>::T *__restrict__ out, int n, int g, int gend,
+                                              int gstride, int nwaves, int wave, bool setup, unsigned char *smem) {
   using T = typename PathT<P>::T;
   using Acc4 = typename PathT<P>::Acc4;
   using Tile = XTile<P, VEC>;
@@ -287,8 +291,6 @@ __global__ __launch_bounds__(512) void k_eval_resident(DevProb pb, const typenam
   using R = RotOps<P>;
   constexpr int NB = blocks_of(P);
   constexpr int ROWS = Tile::ROWS;
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int nwaves = blockDim.x >> 6;
   const LdsLayout L = lds_layout(P, pb, nwaves);
   const unsigned char *s_q = smem + L.q;
   const uint16_t *s_goff = reinterpret_cast<const uint16_t *>(smem + L.goff);
@@ -299,30 +301,26 @@ __global__ __launch_bounds__(512) void k_eval_resident(DevProb pb, const typenam
 
   const int D = pb.D, S = pb.S, MT = pb.MT;
   const int lane = threadIdx.x & 63;
-  // wave-uniform values live in scalar registers: the row-group loop and the buffer
-  // resources built from it stay scalar
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r = lane & 15, q = lane >> 4;
-  const int ngroups = (n + ROWS - 1) / ROWS;
   const int nload = (ROWS * D + 64 * Tile::NV - 1) / (64 * Tile::NV);
-  const int gstride = gridDim.x * nwaves;
-  int g = blockIdx.x * nwaves + wave;
 
   // the first row group's loads go out before the tables are copied
   Tile xt;
-  if (g < ngroups) xt.load(rows_rsrc(x, g * ROWS, n, D), nload, lane);
-  if (ROT) {
-    copy_to_lds(smem + L.q, pb.qfrag, L.q_bytes);
-    copy_to_lds(smem + L.goff, pb.goff, L.goff_bytes);
-  }
-  copy_to_lds(smem + L.oh, pb.oh, L.vec_bytes);
-  copy_to_lds(smem + L.cz, pb.cz, L.mp_bytes);
-  if (KT_::needs_coef) copy_to_lds(smem + L.coef, pb.coef, L.mp_bytes);
-  if (KT_::pairwise) copy_to_lds(smem + L.succ, pb.succ, L.succ_bytes);
+  if (g < gend) xt.load(rows_rsrc(x, g * ROWS, n, D), nload, lane);
   T *Y = reinterpret_cast<T *>(smem + L.y + wave * L.slice_bytes);
-  // columns D..S-1 of every row are zero: the gather's padding slot and the unrotated read-out
-  for (int i = lane; i < ROWS * (S - D); i += 64) Y[(i / (S - D)) * S + D + i % (S - D)] = T(0);
-  __syncthreads();
+  if (setup) {
+    if (ROT) {
+      copy_to_lds(smem + L.q, pb.qfrag, L.q_bytes);
+      copy_to_lds(smem + L.goff, pb.goff, L.goff_bytes);
+    }
+    copy_to_lds(smem + L.oh, pb.oh, L.vec_bytes);
+    copy_to_lds(smem + L.cz, pb.cz, L.mp_bytes);
+    if (KT_::needs_coef) copy_to_lds(smem + L.coef, pb.coef, L.mp_bytes);
+    if (KT_::pairwise) copy_to_lds(smem + L.succ, pb.succ, L.succ_bytes);
+    // columns D..S-1 of every row are zero: the gather's padding slot and the unrotated read-out
+    for (int i = lane; i < ROWS * (S - D); i += 64) Y[(i / (S - D)) * S + D + i % (S - D)] = T(0);
+    __syncthreads();
+  }
 
   const T scale = T(pb.scale);
   const T prm = kind_param<KIND, T>(pb.Df, pb.kparam);
@@ -330,13 +328,13 @@ __global__ __launch_bounds__(512) void k_eval_resident(DevProb pb, const typenam
   const int bstride = kRowsPerBlock * S * static_cast<int>(sizeof(T));
   const int4 *mtab = reinterpret_cast<const int4 *>(pb.mtab);
 
-  for (; g < ngroups; g += gstride) {
+  for (; g < gend; g += gstride) {
     const int row0 = g * ROWS;
     wave_sync();
     xt.stage(nload, D, S, Y, s_oh, lane);
     // the next row group's loads are in flight during everything below
     const int gn = g + gstride;
-    if (gn < ngroups) xt.load(rows_rsrc(x, gn * ROWS, n, D), nload, lane);
+    if (gn < gend) xt.load(rows_rsrc(x, gn * ROWS, n, D), nload, lane);
     wave_sync();
 
     typename R::Frag bf[R::NTERM][NB][R::KTMAX];
@@ -438,6 +436,20 @@ __global__ __launch_bounds__(512) void k_eval_resident(DevProb pb, const typenam
       }
     }
   }
+}
+
+template <int P, int KIND, int ROT, int VEC>
+__global__ __launch_bounds__(512) void k_eval_resident(DevProb pb, const typename PathT<P>::T *__restrict__ x,
+                                                       typename PathT<P>::T *__restrict__ out, int n) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int nwaves = blockDim.x >> 6;
+  // wave-uniform values live in scalar registers: the row-group loop and the buffer
+  // resources built from it stay scalar
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  constexpr int ROWS = XTile<P, VEC>::ROWS;
+  const int ngroups = (n + ROWS - 1) / ROWS;
+  resident_eval<P, KIND, ROT, VEC>(pb, x, out, n, blockIdx.x * nwaves + wave, ngroups, gridDim.x * nwaves, nwaves,
+                                   wave, true, smem);
 }
 
 // Kernel table of one path: index ((kind * 2) + rot) * 2 + vec.

@@ -80,12 +80,24 @@ bool kind_pair_wraps(int kind) { return kind == K_GRIEROSEN || kind == K_F6; }
 // 1e6-weighted single components of elliptic and discus, the plateaus of step, the 3^k
 // and 2^j frequencies of Weierstrass and Katsuura, the phases 50 w^0.2 (Schaffer F7) and
 // g2(z_i, z_{i+1}) (Griewank-Rosenbrock), and the jumps of the rotated Schwefel g1 at
-// |w| = 1000, 1500, ...  For these the split rotation uses six BF16 products.
-bool needs_six_products(int base) {
+// |w| = 1000, 1500, ...  For these the split rotation uses six BF16 products.  Rosenbrock's
+// pair term amplifies the z error by up to |400 z_i (z_i^2 - z_{i+1})| / f; the three-product
+// rotation (z error ~ 2^-16 |z|) meets the FP32 bar once several pairs average their errors,
+// but not with one or a few pairs, so low dimensions get six products as well.
+bool needs_six_products(int base, int n) {
   switch (base) {
     case 2: case 3: case 7: case 8: case 12: case 13: case 16: case 17: return true;
+    case 14: return n < 10;
     default: return false;
   }
+}
+
+bool problem_needs_six(const Problem &p) {
+  for (const Segment &sg : p.segs)
+    if (needs_six_products(sg.base, sg.n)) return true;
+  for (const Problem &c : p.comps)
+    if (problem_needs_six(c)) return true;
+  return false;
 }
 
 // The elliptic and powers exponents (i-1)/(n-1) and the F7 mean over n-1 pairs need n >= 2.

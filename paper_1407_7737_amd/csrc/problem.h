@@ -42,7 +42,8 @@ const FnSpec &fn_spec(int base);  // base in 0..22
 bool kind_is_pairwise(int kind);
 bool kind_pair_wraps(int kind);
 int min_dimension(int base);  // smallest dimension the formula is defined for
-bool needs_six_products(int base);  // FP32 split mode: formulas that get the six-product rotation
+// FP32 split mode: formulas (at the dimension n the formula sees) that get the six-product rotation
+bool needs_six_products(int base, int n);
 
 // SplitMix64 stream (Steele, Lea & Flood 2014) with Marsaglia-polar normals.
 class Rng {
@@ -98,6 +99,9 @@ Problem make_hybrid(int dim, uint64_t seed, uint32_t key, int ngroups, const int
 Problem make_composition(int dim, uint64_t seed, uint32_t key, int ncomp, const int *bases, const double *sigma,
                          const double *lambda, const double *bias);
 Problem make_tab1(int fid, int dim, uint64_t seed);  // any id 0..36
+
+// Split mode on a whole problem: six products when any of its formulas needs them.
+bool problem_needs_six(const Problem &p);
 
 // Dense D x D rotation of a basic problem in original variable order (identity if unrotated).
 std::vector<double> dense_rotation(const Problem &p);

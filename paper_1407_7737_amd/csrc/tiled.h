@@ -1,0 +1,78 @@
+// tiled.h -- the tiled evaluation path: basic functions above the resident kernel's dimension
+// range and every hybrid function (Sec. 5).  Device tables, host builder, launchers.
+//
+// The packed variable space is cut into rotation blocks (the three groups of Sec. 1.2, or the
+// hybrid groups of Sec. 5), each padded to a multiple of 32 positions so that no MFMA tile
+// straddles two blocks.  A workgroup computes one tile of 64 population rows x up to 64 outputs
+// of one block, applies the formula and leaves compensated per-row partial sums in a scratch
+// buffer; a second kernel combines the partials of each formula segment per row.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "devprob.h"
+#include "problem.h"
+
+namespace curob {
+
+constexpr int kTileRows = 64;      // population rows per workgroup tile
+constexpr int kTileK = 32;         // packed positions staged per k step
+constexpr int kGroupMTiles = 4;    // m-tiles (of 16 outputs) per workgroup, one per wave
+constexpr int kPartialSlots = 8;   // per (row, output group): s0 c0 s1 c1 s2 c2 product pad
+constexpr int kMaxSegments = 16;   // formula segments per tiled problem
+constexpr int kChunkRows = 65536;  // rows per pass (bounds the scratch buffers)
+
+struct TiledSeg {
+  int kind;      // formula family of the segment
+  int base;      // Tab. 1 id
+  int g0, g1;    // output groups [g0, g1) of this segment
+  int p0, p1;    // padded positions [p0, p1)
+  int n;         // dimension the formula sees
+  int pairwise;  // 1: terms need z of the successor
+  double kparam; // family parameter (Katsuura exponent)
+  double padc[3];
+};
+
+// One output group: m-tiles [m0, m0 + count) of a block.
+struct TiledGroup {
+  int block, m0, count, seg;
+};
+
+struct TiledProb {
+  // device pointers
+  const int *gidx;      // padded position -> original variable, -1 for padding (Dp entries)
+  const void *oh;       // shift rounded to the path's type (D entries)
+  const void *cz;       // c' per padded position
+  const void *coef;     // coefficient per padded position
+  const int *succ;      // successor padded position (pairwise) or -1
+  const void *qfrag;    // dense tiles of s*Q per block, MFMA A-operand order
+  const int4 *blocks;   // per block: padded offset, padded size, first tile, k-tiles
+  const int4 *groups;   // per output group: block, first m-tile, m-tile count, segment
+  int D, Dp, nblocks, ngroups, nsegs;
+  int any_pairwise;
+  double bias;
+  TiledSeg segs[kMaxSegments];
+};
+
+struct TiledDev {
+  std::vector<void *> allocs;
+  TiledProb tp{};
+  bool ready = false;
+  void release();
+};
+
+// Builds and uploads the tiled tables of a basic or hybrid problem for one path.
+hipError_t build_tiled(const Problem &p, int path, TiledDev &td, std::string &err);
+
+// Scratch the tiled kernels need for one chunk of rows: partial sums and (pairwise) z.
+size_t tiled_partials_bytes(const TiledProb &tp, int path);
+size_t tiled_z_bytes(const TiledProb &tp, int path);
+
+// Evaluates rows [0, n) of x (n <= kChunkRows) into out using the scratch buffers.
+hipError_t launch_tiled(int path, int kind_hint, const TiledProb &tp, const void *x, void *out, int n, void *partials,
+                        void *zbuf, hipStream_t st);
+
+}  // namespace curob

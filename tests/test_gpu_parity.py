@@ -19,8 +19,12 @@ pytestmark = pytest.mark.gpu
 TOL64 = 1e-10
 TOL32 = 1e-4
 SEED = 0
-# formulas the default split mode evaluates with six BF16 products
+# formulas the default split mode evaluates with six BF16 products (Rosenbrock below D = 10)
 SIX_PRODUCTS = {2, 3, 7, 8, 12, 13, 16, 17}
+
+
+def six(fid, dim):
+    return fid in SIX_PRODUCTS or (fid == 14 and dim < 10)
 
 
 def say(*a):
@@ -120,7 +124,7 @@ def test_all_basic_functions_all_paths(env, dim):
         check32(orc, fid, p, x32w, f[c.MODE_SPLIT], ref32, "split")
         check32(orc, fid, p, x32w, f[c.MODE_FP32], ref32, "fp32")
         check32(orc, fid, p, x32w, f[c.MODE_SPLIT_BF16X6], ref32, "split-x6")
-        if fid not in SIX_PRODUCTS:
+        if not six(fid, dim):
             check32(orc, fid, p, x32w, f[c.MODE_SPLIT_BF16X3], ref32, "split-x3")
         else:
             assert np.all(np.isfinite(f[c.MODE_SPLIT_BF16X3]))

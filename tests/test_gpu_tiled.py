@@ -1,0 +1,259 @@
+"""GPU parity of the tiled path (basic functions above the resident kernel's dimension range,
+hybrid functions of Sec. 5) and of compositions (Sec. 6), against the FP64 oracle.
+
+Same bars as the resident-kernel parity tests: FP64 path |f - f_oracle| <= 1e-10 max(1, |f|),
+FP32 paths <= 1e-4 max(1, |f|).  Step and Schwefel's g1 are discontinuous: a component of z
+within the FP32 path's rounding of a plateau edge (Step, jump 2|k| + 1 at z = k + 1/2) or of a
+g1 jump (|w| = 1000, 1500, ...; jump below 500) may land on either side.  Each such component
+adds its jump (times the component's lambda in a composition) to that row's allowance; rows
+with no such component meet the plain bar.  With D = 1000 most Step rows have one.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+TOL32 = 1e-4
+SEED = 0
+SCHWEFEL_SHIFT = 420.9687462275036
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    assert torch.cuda.is_available(), "needs a GPU"
+    import paper_1407_7737_amd as c
+    import oracle
+    state = {"dim": None}
+
+    def use(dim, maxc=1 << 16, seed=SEED):
+        if state["dim"] != (dim, maxc, seed):
+            if state["dim"] is not None:
+                c.dispose()
+            c.initialize(dim, maxc, seed)
+            state["dim"] = (dim, maxc, seed)
+
+    yield c, oracle, torch, use
+    if state["dim"] is not None:
+        c.dispose()
+
+
+def rel_err(f, ref):
+    f = np.asarray(f, dtype=np.float64)
+    return np.abs(f - ref) / np.maximum(1.0, np.abs(ref))
+
+
+def edge_jumps(base, z, y):
+    """Per row: the summed jumps of the components of z within FP32 rounding (64 ulp of |y|, a
+    generous bound of the rotation's error) of a discontinuity of formula base."""
+    delta = 64.0 * 2.0 ** -24 * (1.0 + np.linalg.norm(y, axis=1, keepdims=True))
+    if base == 7:
+        t = z + 0.5
+        k = np.round(t)
+        return np.where(np.abs(t - k) < delta, 2.0 * np.abs(k) + 1.0, 0.0).sum(axis=1)
+    if base in (15, 16):
+        w = np.abs(z + SCHWEFEL_SHIFT)
+        d = np.where(w >= 750.0, np.abs(w - 500.0 * np.round(w / 500.0)), np.inf)
+        return np.where(d < delta, 500.0, 0.0).sum(axis=1)
+    return np.zeros(z.shape[0])
+
+
+def basic_allowance(orc, base, o, R, x):
+    s, cst, _ = orc.XFORM[base]
+    y = s * (x - o[None, :])
+    return edge_jumps(base, y @ R.T + cst, y)
+
+
+def hybrid_allowance(orc, p, bases, x):
+    perm, sizes, blocks = p.hybrid_parts()
+    y = (x - p.shift()[None, :])[:, perm]
+    allow = np.zeros(x.shape[0])
+    off = 0
+    for b, n, Q in zip(bases, sizes, blocks):
+        s, cst, _ = orc.XFORM[b]
+        yg = s * y[:, off:off + n]
+        allow += edge_jumps(b, yg @ Q.T + cst, yg)
+        off += n
+    return allow
+
+
+def check32(f, ref, allow, tag):
+    f = np.asarray(f, dtype=np.float64)
+    assert np.all(np.isfinite(f)), tag
+    bar = TOL32 * np.maximum(1.0, np.abs(ref))
+    d = np.abs(f - ref)
+    assert np.all(d <= bar + allow), (tag, int(np.argmax(d - bar - allow)), float(np.max((d - allow) / bar)))
+    e = np.where(allow > 0, 0.0, d / np.maximum(1.0, np.abs(ref)))
+    return float(e.max())
+
+
+def run_paths(c, torch, fid, x64, modes):
+    x32 = x64.astype(np.float32)
+    f64 = c.func_evaluate(fid, torch.from_numpy(x64).cuda()).cpu().numpy()
+    out = {}
+    dx32 = torch.from_numpy(x32).cuda()
+    for m in modes:
+        c.set_mode(m)
+        out[m] = c.func_evaluatef(fid, dx32).cpu().numpy()
+    c.set_mode(c.MODE_SPLIT)
+    torch.cuda.synchronize()
+    return x32.astype(np.float64), f64, out
+
+
+def all_modes(c):
+    return [c.MODE_SPLIT, c.MODE_FP32, c.MODE_SPLIT_BF16X3, c.MODE_SPLIT_BF16X6]
+
+
+SIX_PRODUCTS = {2, 3, 7, 8, 12, 13, 16, 17}
+
+
+def six(fid, dim):
+    return fid in SIX_PRODUCTS or (fid == 14 and dim < 10)
+
+
+@pytest.mark.parametrize("dim", [129, 200, 1000])
+def test_large_dim_basic_all_paths(env, dim):
+    """Every Tab. 1 formula above the resident range: 200 rows = three 64-row tiles and a
+    ragged tail of 8; rotation blocks padded to 32 leave ragged k tiles."""
+    c, orc, torch, use = env
+    use(dim)
+    from paper_1407_7737_amd.inputs import population, near
+    n = 200
+    for fid in range(23):
+        say(f"[tiled] dim={dim} fid={fid} n={n}")
+        p = orc.basic(fid, dim, SEED)
+        x = population(n, dim, seed=fid)
+        x[:40] = near(np.repeat(p.shift()[None, :], 40, axis=0), 0.5, seed=fid)
+        x32w, f64, f = run_paths(c, torch, fid, x, all_modes(c))
+        e64 = rel_err(f64, p(x, threads=16)).max()
+        assert e64 <= TOL64, (fid, dim, e64)
+        ref32 = p(x32w, threads=16)
+        allow = basic_allowance(orc, fid, p.shift(), p.rotation(), x32w)
+        check32(f[c.MODE_SPLIT], ref32, allow, ("split", dim, fid))
+        check32(f[c.MODE_FP32], ref32, allow, ("fp32", dim, fid))
+        check32(f[c.MODE_SPLIT_BF16X6], ref32, allow, ("x6", dim, fid))
+        if not six(fid, dim):
+            check32(f[c.MODE_SPLIT_BF16X3], ref32, allow, ("x3", dim, fid))
+
+
+HYBRID_BASES = {23: [15, 10, 2], 24: [4, 21, 10], 25: [9, 8, 14, 22], 26: [21, 3, 13, 10],
+                27: [22, 21, 14, 15, 2], 28: [17, 20, 13, 15, 19]}
+
+
+@pytest.mark.parametrize("dim", [10, 30, 100, 1000])
+def test_paper_hybrids(env, dim):
+    """The six hybrid functions of Sec. 5 (ids 23-28)."""
+    c, orc, torch, use = env
+    use(dim)
+    from paper_1407_7737_amd.inputs import population
+    n = 200
+    for fid in range(23, 29):
+        say(f"[hybrid] dim={dim} fid={fid}")
+        p = orc.fid_problem(fid, dim, SEED)
+        x = population(n, dim, seed=fid)
+        x32w, f64, f = run_paths(c, torch, fid, x, [c.MODE_SPLIT, c.MODE_FP32, c.MODE_SPLIT_BF16X6])
+        e64 = rel_err(f64, p(x, threads=16)).max()
+        assert e64 <= TOL64, (fid, dim, e64)
+        ref32 = p(x32w, threads=16)
+        allow = hybrid_allowance(orc, p, HYBRID_BASES[fid], x32w)
+        for m in f:
+            check32(f[m], ref32, allow, (m, dim, fid))
+
+
+@pytest.mark.parametrize("dim", [10, 30, 100, 1000])
+def test_paper_compositions(env, dim):
+    """The eight composition functions of Sec. 6 (ids 29-36), with their optimum at the origin
+    for the third component; rows include points at and near every component optimum."""
+    c, orc, torch, use = env
+    use(dim)
+    from paper_1407_7737_amd.inputs import population, near
+    n = 200 if dim < 1000 else 100
+    for fid in range(29, 37):
+        say(f"[composition] dim={dim} fid={fid}")
+        p = orc.fid_problem(fid, dim, SEED)
+        x = population(n, dim, seed=fid)
+        ncomp = 3 if fid in (30, 31, 35, 36) else 5
+        for i in range(ncomp):
+            o = p.shift(i)
+            x[i] = o  # exactly at an optimum: one-hot weights
+            x[10 + i] = near(o[None, :], 1.0, seed=i)[0]
+        x32w, f64, f = run_paths(c, torch, fid, x, [c.MODE_SPLIT, c.MODE_FP32])
+        ref = p(x, threads=16)
+        e64 = rel_err(f64, ref).max()
+        assert e64 <= TOL64, (fid, dim, e64)
+        ref32 = p(x32w, threads=16)
+        for m in f:
+            e = rel_err(f[m], ref32)
+            assert np.all(np.isfinite(f[m])), (m, fid)
+            # discontinuous components (Step, Schwefel) may flip rows at their edges
+            assert (e <= TOL32).mean() >= 0.98, (m, dim, fid, float((e <= TOL32).mean()))
+            say(f"[composition] dim={dim} fid={fid} mode={m} max {e.max():.3e} median {np.median(e):.3e}")
+
+
+def test_hybrid_d1000_n16384(env):
+    """Hybrid workload at D = 1000, N = 16384 (3-5 groups, Dirichlet(2) proportions, a
+    different rotated/unrotated formula per group), every row against the oracle."""
+    c, orc, torch, use = env
+    use(1000, maxc=16384)
+    from paper_1407_7737_amd.inputs import hybrid_params, population
+    bases, props = hybrid_params(1000, seed=0)
+    say(f"[hybrid-full] bases={bases} p={[round(v, 3) for v in props]}")
+    c.define_hybrid(100, bases, props)
+    p = orc.hybrid(100, 1000, SEED, bases, props)
+    x = population(16384, 1000, seed=1)
+    x32w, f64, f = run_paths(c, torch, 100, x, [c.MODE_SPLIT, c.MODE_FP32])
+    assert rel_err(f64, p(x, threads=16)).max() <= TOL64
+    ref32 = p(x32w, threads=16)
+    allow = hybrid_allowance(orc, p, bases, x32w)
+    for m in f:
+        say(f"[hybrid-full] mode={m} max {check32(f[m], ref32, allow, m):.3e}")
+
+
+def test_composition_d1000_n16384(env):
+    """Composition workload at D = 1000, N = 16384: the eight rotated/unrotated formulas,
+    sigma ~ U[10, 50], lambda log-uniform in [1e-6, 1], bias 100 i, FP64 weights.  All rows
+    on the FP32 split path; the FP64 path on a 2048-row sample the oracle finishes quickly."""
+    c, orc, torch, use = env
+    use(1000, maxc=16384)
+    from paper_1407_7737_amd.inputs import composition_params, population, near
+    bases, sigma, lam, bias = composition_params(seed=0)
+    c.define_composition(101, bases, sigma, lam, bias)
+    p = orc.composition(101, 1000, SEED, bases, sigma, lam, bias)
+    x = population(16384, 1000, seed=2)
+    for i in range(8):
+        x[i] = p.shift(i)
+        x[100 + i] = near(p.shift(i)[None, :], 2.0, seed=i)[0]
+    x32w, f64, f = run_paths(c, torch, 101, x, [c.MODE_SPLIT, c.MODE_FP32])
+    rows = np.r_[0:256, np.linspace(256, 16383, 1792).astype(int)]
+    assert rel_err(f64[rows], p(x[rows], threads=16)).max() <= TOL64
+    ref32 = p(x32w, threads=16)
+    allow = np.zeros(x.shape[0])
+    for i, b in enumerate(bases):
+        if b in (7, 15, 16):
+            allow += lam[i] * basic_allowance(orc, b, p.shift(i), p.rotation(i), x32w)
+    for m in f:
+        say(f"[composition-full] mode={m} max {check32(f[m], ref32, allow, m):.3e}")
+
+
+def test_tiled_scratch_reuse_and_chunking(env):
+    """More rows than one scratch chunk (65536) on the tiled path: rows on both sides of the
+    chunk boundary match the oracle, and a second problem reusing the scratch is unaffected."""
+    c, orc, torch, use = env
+    use(200, maxc=70000)
+    from paper_1407_7737_amd.inputs import population
+    n = 65536 + 300
+    x = population(n, 200, seed=7)
+    rows = np.r_[0:64, 65472:n]
+    for fid in (14, 19):
+        say(f"[chunk] fid={fid} n={n}")
+        p = orc.basic(fid, 200, SEED)
+        f = c.func_evaluate(fid, torch.from_numpy(x).cuda()).cpu().numpy()
+        assert rel_err(f[rows], p(x[rows])).max() <= TOL64, fid
