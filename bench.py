@@ -8,16 +8,25 @@ points for comparison.  Kernel durations come from HIP events recorded on the li
 around every launch of the timed region; the roofline figure uses the algorithmic bytes of
 the dominant kernel (D*4 bytes read + 4 bytes written per row).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+Secondary workloads (reported under "secondary", not in "value"): the D = 1000, N = 2^18 form
+of the same eight formulas; a hybrid and a composition at D = 1000, N = 16384; 64 batched
+populations in one persistent launch (graph replay, direct launch, one call per population).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-secondary]
+                    [--copy-probe]
+    python bench.py --pmc-summary FETCH_DIR WRITE_DIR   (writes profiles/traffic_d100_n262144.*)
 
 Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -31,9 +40,14 @@ N = 1 << 18
 FIDS = [0, 2, 9, 10, 11, 14, 16, 19]
 NAMES = {0: "sphere", 2: "elliptic", 9: "griewank", 10: "rastrigin_u", 11: "rastrigin", 14: "rosenbrock",
          16: "schwefel", 19: "ackley"}
+# resident kernel instance (path, formula family, rotated) each formula runs at D = 100 in the
+# default split mode: path 0 = three BF16 products, 3 = six; the sphere skips its rotation
+RESIDENT_KERNEL = {0: (0, 0, 0), 2: (3, 0, 1), 9: (0, 5, 1), 10: (0, 6, 0), 11: (0, 6, 1), 14: (0, 9, 1),
+                   16: (3, 10, 1), 19: (0, 13, 1)}
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_d100_n262144.json")
 KERNEL_SOURCES = ["eval_resident.h", "formulas.h", "devprob.h", "kernels.h"]
+COPY_PROBE_BYTES = N * DIM * 4  # the probe reads the FP32 population once and writes it once
 
 
 def kernel_source_hash() -> str:
@@ -44,9 +58,14 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel_name: str, launch_bytes: float):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or None when the
-    kernel sources changed since the counters were taken."""
+def resident_key(fid: int) -> str:
+    p, k, r = RESIDENT_KERNEL[fid]
+    return f"k_eval_resident<{p},{k},{r},{1 if DIM % 4 == 0 else 0}>"
+
+
+def measured_traffic(fid: int):
+    """HBM bytes per launch of the formula's kernel from the committed rocprofv3 counter
+    summary, or None when the kernel sources changed since the counters were taken."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -54,7 +73,7 @@ def measured_traffic(kernel_name: str, launch_bytes: float):
         return None
     if t.get("kernel_source_hash") != kernel_source_hash():
         return None
-    k = t.get("kernels", {}).get(kernel_name)
+    k = t.get("kernels", {}).get(resident_key(fid))
     return None if k is None else k.get("hbm_bytes_per_launch")
 
 
@@ -88,13 +107,162 @@ def cpu_baseline(x32: np.ndarray, budget_s: float = 12.0):
     }
 
 
+def event_time_ms(torch, fn, reps: int, warmup: int = 2) -> float:
+    """Mean time of fn() on the current stream from HIP events around the repeated launches."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def secondary(torch, c, reps: int = 10) -> dict:
+    """The other workload shapes, timed briefly (kernel time from HIP events)."""
+    from paper_1407_7737_amd.inputs import batch_params, composition_params, hybrid_params, population
+    out = {}
+    dev = torch.device("cuda:0")
+    # D = 1000, N = 2^18: the same eight formulas on the tiled path
+    d, n = 1000, 1 << 18
+    c.initialize(d, n, 0)
+    try:
+        x = torch.from_numpy(population(n, d, seed=0, dtype=np.float32)).to(dev)
+        o = torch.empty(n, dtype=torch.float32, device=dev)
+        per = {}
+        for fid in FIDS:
+            per[NAMES[fid]] = event_time_ms(torch, lambda: c.func_evaluatef(fid, x, out=o), reps)
+        tot = sum(per.values())
+        out["d1000_n262144"] = {"evals_per_s": n * len(FIDS) / (tot * 1e-3), "ms_per_function": per,
+                                "hbm_frac_per_function": {k: n * (d * 4 + 4) / (v * 1e-3) / 1e9 / HBM_PEAK_GBS
+                                                          for k, v in per.items()}}
+        del x
+        # hybrid and composition at D = 1000, N = 16384
+        m = 16384
+        xh = torch.from_numpy(population(m, d, seed=1, dtype=np.float32)).to(dev)
+        oh = torch.empty(m, dtype=torch.float32, device=dev)
+        bases, props = hybrid_params(d, seed=0)
+        c.define_hybrid(100, bases, props)
+        cb, sig, lam, bias = composition_params(seed=0)
+        c.define_composition(101, cb, sig, lam, bias)
+        th = event_time_ms(torch, lambda: c.func_evaluatef(100, xh, out=oh), reps)
+        tc = event_time_ms(torch, lambda: c.func_evaluatef(101, xh, out=oh), reps)
+        out["hybrid_d1000_n16384"] = {"evals_per_s": m / (th * 1e-3), "ms": th, "groups": len(bases),
+                                      "bases": bases}
+        out["composition_d1000_n16384"] = {"evals_per_s": m / (tc * 1e-3), "ms": tc, "components": len(cb)}
+    finally:
+        c.dispose()
+    # 64 batched populations
+    c.initialize(10, 2048, 0)
+    try:
+        fids, dims, counts = batch_params(64, seed=0)
+        b = c.Batch(fids, dims, counts, seed=0)
+        xs = [torch.from_numpy(population(int(k), int(dd), seed=i, dtype=np.float32)).to(dev)
+              for i, (dd, k) in enumerate(zip(dims, counts))]
+        outs = [torch.empty(int(k), dtype=torch.float32, device=dev) for k in counts]
+        b.bind(xs, outs)
+        default_shape = b.shape()
+        t_default = event_time_ms(torch, b.run, 50)
+        tuned = b.tune(reps=20)
+        t_graph = event_time_ms(torch, b.run, 50)
+        t_direct = event_time_ms(torch, b.run_direct, 50)
+        b.close()
+        rows = int(sum(counts))
+        out["batch_64"] = {"rows": rows, "graph_ms": t_graph, "direct_ms": t_direct, "untuned_graph_ms": t_default,
+                           "evals_per_s": rows / (t_graph * 1e-3), "tuned_shape": tuned,
+                           "default_shape": default_shape}
+    finally:
+        c.dispose()
+    # one call per population for comparison (the same populations as 64 single evaluations)
+    per_call = 0.0
+    for dd in sorted(set(dims)):
+        idx = [i for i in range(len(dims)) if dims[i] == dd]
+        c.initialize(int(dd), 2048, 0)
+        try:
+            for i in idx:
+                per_call += event_time_ms(torch, lambda: c.func_evaluatef(int(fids[i]), xs[i], out=outs[i]), 20)
+        finally:
+            c.dispose()
+    out["batch_64"]["one_call_per_population_ms"] = per_call
+    return out
+
+
+def pmc_summary(fetch_dir: str, write_dir: str) -> None:
+    """Per-kernel FETCH_SIZE / WRITE_SIZE (KiB per dispatch) from two rocprofv3 --pmc runs of
+    this script with --copy-probe, scaled by what the counters read for the copy of a known
+    number of bytes; writes profiles/traffic_d100_n262144.{json,txt}."""
+    def load(d, counter):
+        vals = {}
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for row in csv.DictReader(open(f)):
+                if row["Counter_Name"] != counter:
+                    continue
+                vals.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]))
+        return vals
+
+    def short(name):
+        m = (re.search(r"k_eval_residentILi(\d+)ELi(\d+)ELi(\d+)ELi(\d+)E", name)
+             or re.search(r"k_eval_resident<(\d+), (\d+), (\d+), (\d+)>", name))
+        if m:
+            return "k_eval_resident<{},{},{},{}>".format(*m.groups())
+        return None
+
+    fetch, write = load(fetch_dir, "FETCH_SIZE"), load(write_dir, "WRITE_SIZE")
+    copy_f = [v for k, vs in fetch.items() if "neg" in k.lower() for v in vs]
+    copy_w = [v for k, vs in write.items() if "neg" in k.lower() for v in vs]
+    cf = COPY_PROBE_BYTES / (float(np.median(copy_f)) * 1024.0)
+    cw = COPY_PROBE_BYTES / (float(np.median(copy_w)) * 1024.0)
+    kernels = {}
+    for name in set(fetch) | set(write):
+        key = short(name)
+        if key is None:
+            continue
+        f = fetch.get(name, [])
+        w = write.get(name, [])
+        fk = float(np.median(f)) if f else 0.0
+        wk = float(np.median(w)) if w else 0.0
+        kernels[key] = {"fetch_kib": fk, "write_kib": wk, "hbm_bytes_per_launch": fk * 1024 * cf + wk * 1024 * cw}
+    algo = N * (DIM * 4 + 4)
+    res = {"kernel_source_hash": kernel_source_hash(), "copy_probe_bytes": COPY_PROBE_BYTES,
+           "fetch_scale": cf, "write_scale": cw, "algorithmic_bytes_fp32": algo, "kernels": kernels}
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(res, f, indent=1, sort_keys=True)
+    lines = ["HBM traffic per launch, D=100, N=2^18 (rocprofv3 --pmc, one counter per run)", "",
+             "commands (from the repository root):",
+             "  rocprofv3 --pmc FETCH_SIZE --output-format csv -d <FETCH_DIR> -- python bench.py --steps 2 --warmup 1"
+             " --no-cpu-baseline --no-secondary --copy-probe",
+             "  rocprofv3 --pmc WRITE_SIZE --output-format csv -d <WRITE_DIR> -- python bench.py --steps 2 --warmup 1"
+             " --no-cpu-baseline --no-secondary --copy-probe",
+             "  python bench.py --pmc-summary <FETCH_DIR> <WRITE_DIR>", "",
+             f"copy probe: {COPY_PROBE_BYTES} bytes read and written; counter scale fetch {cf:.4f}, write {cw:.4f}",
+             f"algorithmic bytes per FP32 launch: {algo}", "",
+             f"{'kernel':34s} {'FETCH KiB':>12s} {'WRITE KiB':>12s} {'HBM bytes':>14s} {'/ algorithmic':>14s}"]
+    for k in sorted(kernels):
+        v = kernels[k]
+        lines.append(f"{k:34s} {v['fetch_kib']:12.0f} {v['write_kib']:12.0f} {v['hbm_bytes_per_launch']:14.0f} "
+                     f"{v['hbm_bytes_per_launch'] / algo:14.3f}")
+    with open(TRAFFIC_FILE.replace(".json", ".txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(*args.pmc_summary)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only: the population shards by rows "
                                    "with no exchange, so N GPUs would each run this same single-GPU workload"}))
@@ -144,6 +312,14 @@ def main():
     wall32, per32 = timed(False)
     wall64, per64 = timed(True)
     c.dispose()
+    if args.copy_probe:
+        # a plain streaming kernel of known traffic (reads and writes the FP32 population once),
+        # for scaling the HBM byte counters; negation gives it a name found nowhere else
+        buf = torch.empty_like(x32)
+        for _ in range(3):
+            torch.neg(x32, out=buf)
+        torch.cuda.synchronize()
+        del buf
 
     ms32 = wall32 / args.steps * 1e3
     ms64 = wall64 / args.steps * 1e3
@@ -153,12 +329,12 @@ def main():
     bytes64 = N * (DIM * 8 + 8)
     dom = max(FIDS, key=lambda f: per32[f])
     ach = bytes32 / (per32[dom] * 1e-3) / 1e9
-    kname = f"split:{NAMES[dom]}"
-    traffic = measured_traffic(kname, bytes32)
+    traffic = measured_traffic(dom)
     per_fn = {NAMES[f]: {"split_ms": round(per32[f], 5), "fp64_ms": round(per64[f], 5),
                          "split_evals_per_s": N / (per32[f] * 1e-3), "fp64_evals_per_s": N / (per64[f] * 1e-3),
                          "split_hbm_frac": bytes32 / (per32[f] * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                         "fp64_hbm_frac": bytes64 / (per64[f] * 1e-3) / 1e9 / HBM_PEAK_GBS} for f in FIDS}
+                         "fp64_hbm_frac": bytes64 / (per64[f] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "kernel": resident_key(f)} for f in FIDS}
     res = {
         "metric": "evals/sec at D=100,N=2^18: split-BF16 MFMA vs FP64 path; % of roofline",
         "value": value,
@@ -177,11 +353,15 @@ def main():
                                "func_evaluatef default split-BF16 mode",
                    "dim": DIM, "rows": N, "functions": len(FIDS)},
         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "kernel": kname},
+                     "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "kernel": resident_key(dom),
+                     "function": NAMES[dom], "algorithmic_bytes_per_launch": bytes32,
+                     "avg_launch_ms": per32[dom]},
         "fp64_path": {"value": evals * args.steps / wall64, "unit": "evals/s", "ms_per_step": ms64,
                       "split_over_fp64": (evals * args.steps / wall32) / (evals * args.steps / wall64)},
         "per_function": per_fn,
     }
+    if not args.no_secondary:
+        res["secondary"] = secondary(torch, c)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(x32h)
     print(json.dumps(res), flush=True)

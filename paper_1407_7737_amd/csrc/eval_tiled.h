@@ -100,6 +100,44 @@ __device__ __forceinline__ int nsum_any(int kind) {
                               : 1;
 }
 
+// Formula and row sums of one wave's m-tile for its four 16-row column blocks; the four lanes
+// of a row combine their sums and lane group 0 leaves them in the wave's LDS slots.
+template <int P, int K>
+__device__ __forceinline__ void reduce_tile(const typename Types<P>::Acc4 (&acc)[4], const typename Types<P>::T (&zc)[4],
+                                            const typename Types<P>::T (&cf)[4], typename Types<P>::T prm,
+                                            typename Types<P>::T *red, int r, int q) {
+  using T = typename Types<P>::T;
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) {
+    Acc<T> a;
+    a.init();
+    T v[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) phi<K, T>(v, a.p, T(acc[cb][e]) + zc[e], T(0), cf[e], prm);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) a.add(k, v[k]);
+#pragma unroll
+    for (int sh = 16; sh <= 32; sh <<= 1) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const T so = __shfl_xor(a.s[k], sh, 64);
+        const T co = __shfl_xor(a.c[k], sh, 64);
+        acc_merge(a, k, so, co);
+      }
+      a.p *= __shfl_xor(a.p, sh, 64);
+    }
+    if (q == 0) {
+      T *dst = red + (16 * cb + r) * kPartialSlots;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        dst[2 * k] = a.s[k];
+        dst[2 * k + 1] = a.c[k];
+      }
+      dst[6] = a.p;
+    }
+  }
+}
+
 // KIND >= 0: one formula family for every segment (basic functions); KIND < 0: the family of
 // each output group's segment is read at run time (hybrids).
 template <int P, int KIND>
@@ -241,7 +279,6 @@ __global__ __launch_bounds__(256) void k_tiled_partial(TiledProb tp, const typen
         }
       }
     } else {
-      const T prm = KIND >= 0 ? kind_param<(KIND >= 0 ? KIND : 0), T>(sg.n, sg.kparam) : param_any<T>(kind, sg.n, sg.kparam);
       T zc[4], cf[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
@@ -249,38 +286,20 @@ __global__ __launch_bounds__(256) void k_tiled_partial(TiledProb tp, const typen
         zc[e] = cz[pp];
         cf[e] = coefp[pp];
       }
-#pragma unroll
-      for (int cb = 0; cb < 4; ++cb) {
-        Acc<T> a;
-        a.init();
-        T v[3] = {T(0), T(0), T(0)};
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          if constexpr (KIND >= 0)
-            phi<(KIND >= 0 ? KIND : 0), T>(v, a.p, T(acc[cb][e]) + zc[e], T(0), cf[e], prm);
-          else
-            phi_any<T>(kind, v, a.p, T(acc[cb][e]) + zc[e], T(0), cf[e], prm);
-        }
-#pragma unroll
-        for (int k = 0; k < 3; ++k) a.add(k, v[k]);
-#pragma unroll
-        for (int sh = 16; sh <= 32; sh <<= 1) {
-#pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            const T so = __shfl_xor(a.s[k], sh, 64);
-            const T co = __shfl_xor(a.c[k], sh, 64);
-            acc_merge(a, k, so, co);
-          }
-          a.p *= __shfl_xor(a.p, sh, 64);
-        }
-        if (q == 0) {
-          T *dst = red + (16 * cb + r) * kPartialSlots;
-#pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            dst[2 * k] = a.s[k];
-            dst[2 * k + 1] = a.c[k];
-          }
-          dst[6] = a.p;
+      if constexpr (KIND >= 0) {
+        reduce_tile<P, KIND>(acc, zc, cf, kind_param<KIND, T>(sg.n, sg.kparam), red, r, q);
+      } else {
+        // hybrids: one branch per wave on the segment's family
+        const T prm = param_any<T>(kind, sg.n, sg.kparam);
+        switch (kind) {
+#define CUROB_RT_CASE(K) \
+  case K: reduce_tile<P, K>(acc, zc, cf, prm, red, r, q); break;
+          CUROB_RT_CASE(K_WSPHERE) CUROB_RT_CASE(K_POWERS) CUROB_RT_CASE(K_SHARPV) CUROB_RT_CASE(K_STEP)
+          CUROB_RT_CASE(K_WEIERSTRASS) CUROB_RT_CASE(K_GRIEWANK) CUROB_RT_CASE(K_RASTRIGIN)
+          CUROB_RT_CASE(K_SCHWEFEL) CUROB_RT_CASE(K_KATSUURA) CUROB_RT_CASE(K_LUNACEK) CUROB_RT_CASE(K_ACKLEY)
+          CUROB_RT_CASE(K_HAPPYCAT) CUROB_RT_CASE(K_HGBAT)
+#undef CUROB_RT_CASE
+          default: break;  // pairwise families store z above
         }
       }
     }
