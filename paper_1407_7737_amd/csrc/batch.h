@@ -21,7 +21,7 @@ namespace curob {
 
 constexpr uint32_t kBatchKeyBase = 2048;  // population i keys its random data by kBatchKeyBase + i
 constexpr int kBatchMaxWaves = 4;
-constexpr int kBatchRows = kRowsPerBlock * 2;  // rows per row group on the FP32 paths
+constexpr int kBatchRows = kRowsPerBlock * blocks_of(PATH_SPLIT);  // rows per row group on the FP32 paths
 
 // The variants (formula family, rotation, six products) the batch kernel runs: one per
 // Tab. 1 function fid (its family and transform, the sphere evaluated without its rotation as

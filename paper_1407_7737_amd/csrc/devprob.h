@@ -26,9 +26,10 @@ constexpr int kMaxMT = 8;          // m-tiles supported by the resident kernel (
 constexpr int kRowsPerBlock = 16;  // population rows per MFMA column block (the MFMA N dimension)
 
 inline constexpr int kw_of(int path) { return is_split(path) ? 32 : 4; }
-// 16-row column blocks a wave evaluates per iteration: two on the FP32 paths, so every rotation
-// tile read from LDS feeds two MFMAs; one on the FP64 path (register budget).
-inline constexpr int blocks_of(int path) { return path == PATH_F64 ? 1 : 2; }
+// 16-row column blocks a wave evaluates per iteration.  One on every path: two would let each
+// rotation tile read from LDS feed two MFMAs, but would double the registers and the LDS slice
+// of a wave and halve the waves a CU holds, and the kernel needs the waves to hide latency.
+inline constexpr int blocks_of(int) { return 1; }
 
 struct DevProb {
   // every pointer is device memory owned by the library

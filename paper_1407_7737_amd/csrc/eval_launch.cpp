@@ -34,7 +34,7 @@ LaunchShape resident_shape(int path, const DevProb &pb, int n, int num_cu) {
   const LdsLayout one = lds_layout(path, pb, 1);
   const int slice = one.total - one.fixed;
   int waves = (kMaxLdsBytes - one.fixed) / slice;
-  if (waves > kMaxWavesPerWG) waves = kMaxWavesPerWG;
+  if (waves > max_waves_of(path)) waves = max_waves_of(path);
   if (waves < 1) waves = 1;
   const int rows = kRowsPerBlock * blocks_of(path);
   const int groups = (n + rows - 1) / rows;

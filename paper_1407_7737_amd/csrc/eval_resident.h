@@ -35,6 +35,8 @@ typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
@@ -181,20 +183,28 @@ __device__ __forceinline__ void gather_b(typename RotOps<P>::Frag (&bf)[RotOps<P
         const uint4 idx = *reinterpret_cast<const uint4 *>(s_goff + kt * 32 + q * 8);
         const uint32_t iw[4] = {idx.x, idx.y, idx.z, idx.w};
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const uint32_t off = (iw[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
+        for (int e = 0; e < 8; e += 2) {
+          // two elements at a time: one packed conversion per term for the pair
+          const uint32_t o0 = iw[e >> 1] & 0xFFFFu, o1 = iw[e >> 1] >> 16;
 #pragma unroll
           for (int b = 0; b < NB; ++b) {
-            const float y = *reinterpret_cast<const float *>(Yb + b * bstride + off);
-            const __bf16 h = (__bf16)y;
-            const float r1 = y - (float)h;
-            bf[0][b][kt][e] = h;
+            const f32x2 y = {*reinterpret_cast<const float *>(Yb + b * bstride + o0),
+                             *reinterpret_cast<const float *>(Yb + b * bstride + o1)};
+            const bf16x2 h = __builtin_convertvector(y, bf16x2);
+            const f32x2 r1 = y - __builtin_convertvector(h, f32x2);
+            bf[0][b][kt][e] = h[0];
+            bf[0][b][kt][e + 1] = h[1];
             if constexpr (R::NTERM == 3) {
-              const __bf16 mm = (__bf16)r1;
-              bf[1][b][kt][e] = mm;
-              bf[2][b][kt][e] = (__bf16)(r1 - (float)mm);
+              const bf16x2 m = __builtin_convertvector(r1, bf16x2);
+              const bf16x2 l = __builtin_convertvector(r1 - __builtin_convertvector(m, f32x2), bf16x2);
+              bf[1][b][kt][e] = m[0];
+              bf[1][b][kt][e + 1] = m[1];
+              bf[2][b][kt][e] = l[0];
+              bf[2][b][kt][e + 1] = l[1];
             } else {
-              bf[1][b][kt][e] = (__bf16)r1;
+              const bf16x2 l = __builtin_convertvector(r1, bf16x2);
+              bf[1][b][kt][e] = l[0];
+              bf[1][b][kt][e + 1] = l[1];
             }
           }
         }
@@ -439,7 +449,7 @@ __device__ __forceinline__ void resident_eval(const DevProb &pb, const typename 
 }
 
 template <int P, int KIND, int ROT, int VEC>
-__global__ __launch_bounds__(512) void k_eval_resident(DevProb pb, const typename PathT<P>::T *__restrict__ x,
+__global__ __launch_bounds__(64 * max_waves_of(P)) void k_eval_resident(DevProb pb, const typename PathT<P>::T *__restrict__ x,
                                                        typename PathT<P>::T *__restrict__ out, int n) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int nwaves = blockDim.x >> 6;

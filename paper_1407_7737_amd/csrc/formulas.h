@@ -172,9 +172,15 @@ __device__ __forceinline__ void phi(T (&v)[3], T &p, T z, T zn, T coef, T prm) {
   } else if constexpr (KIND == K_ACKLEY) {
     v[0] += z * z;
     v[1] += cos_2pi(z);
-  } else if constexpr (KIND == K_HAPPYCAT || KIND == K_HGBAT) {
-    v[0] += z * z;
+  } else if constexpr (KIND == K_HAPPYCAT) {
+    // z^2 - 1 per term: near the optimum z ~ -1 and sum z^2 - n would cancel to ulps of n
+    v[0] += __builtin_fma(z, z, T(-1));
     v[1] += z;
+  } else if constexpr (KIND == K_HGBAT) {
+    // (sum z^2)^2 - (sum z)^2 = sum(z^2 + z) * sum(z^2 - z), each term rounded once: near the
+    // optimum (z ~ -1) the two squares are ~n^2 and cancel, while the factors stay accurate
+    v[0] += __builtin_fma(z, z, z);
+    v[1] += __builtin_fma(z, z, -z);
   } else if constexpr (KIND == K_F6) {
     const T r2 = z * z + zn * zn;
     const T sn = sin_rad(t_sqrt(r2));
@@ -214,14 +220,11 @@ __device__ __forceinline__ T finalize(const T (&s)[3], T p, int n) {
   } else if constexpr (KIND == K_ACKLEY) {
     return T(-20) * t_exp(T(-0.2) * t_sqrt(s[0] / nn)) - t_exp(s[1] / nn) + T(20) + T(2.71828182845904523536);
   } else if constexpr (KIND == K_HAPPYCAT) {
-    const T d = s[0] - nn;
-    return t_pow(t_abs(d), T(0.25)) + (T(0.5) * s[0] + s[1]) / nn + T(0.5);
+    // s[0] = sum(z^2 - 1), s[1] = sum z
+    return t_pow(t_abs(s[0]), T(0.25)) + (T(0.5) * (s[0] + nn) + s[1]) / nn + T(0.5);
   } else if constexpr (KIND == K_HGBAT) {
-    // (sum z^2)^2 - (sum z)^2 factored as (a - |b|)(a + |b|): near the optimum both squares
-    // are ~n^2 and their FP32 difference would cancel to a few ulps of n^2
-    const T b = t_abs(s[1]);
-    const T d = (s[0] - b) * (s[0] + b);
-    return t_sqrt(t_abs(d)) + (T(0.5) * s[0] + s[1]) / nn + T(0.5);
+    // s[0] = sum(z^2 + z), s[1] = sum(z^2 - z): sum z^2 = (s0 + s1)/2, sum z = (s0 - s1)/2
+    return t_sqrt(t_abs(s[0] * s[1])) + (T(0.75) * s[0] - T(0.25) * s[1]) / nn + T(0.5);
   } else {
     return T(0);
   }

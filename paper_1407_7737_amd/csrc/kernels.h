@@ -20,7 +20,13 @@ struct LdsLayout {
 __host__ __device__ inline int round16(int b) { return (b + 15) & ~15; }
 
 constexpr int kMaxLdsBytes = 160 * 1024;  // LDS per workgroup on gfx950
-constexpr int kMaxWavesPerWG = 8;
+// Waves per workgroup of the resident kernel: one 16-row column block per wave, so the per-wave
+// LDS slice is small and up to four waves share a SIMD on the three-product path (<= 128 VGPRs);
+// the six-product path holds a third B term (<= 168 VGPRs, three waves per SIMD) and the FP64
+// path is bound by LDS to about eight waves.
+__host__ __device__ constexpr int max_waves_of(int path) {
+  return path == PATH_F64 ? 8 : (path == PATH_SPLIT6 ? 12 : 16);
+}
 
 // LDS carve of the resident kernel: rotation tiles, gather offsets, per-variable shift,
 // per-position tables, then one slice per wave holding its rows (16 per column block) plus one

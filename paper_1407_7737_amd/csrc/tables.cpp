@@ -205,6 +205,7 @@ bool build_host_tables(const Problem &p, int path, HostTables &ht, std::string &
   pb.padc[0] = pb.padc[1] = pb.padc[2] = 0.0;
   if (kind == K_WEIERSTRASS) pb.padc[0] = -npad * (2.0 - 9.5367431640625e-07);  // sum_k a^k cos(pi 3^k)
   if (kind == K_ACKLEY) pb.padc[1] = npad;                                          // cos(0) = 1
+  if (kind == K_HAPPYCAT) pb.padc[0] = -npad;                                       // 0^2 - 1
   if (kind == K_LUNACEK) {
     pb.padc[0] = 6.25 * npad;  // (0 - 2.5)^2
     pb.padc[1] = 6.25 * npad;  // (0 + 2.5)^2

@@ -220,6 +220,7 @@ hipError_t build_tiled(const Problem &p, int path, TiledDev &td, std::string &er
     ts.padc[0] = ts.padc[1] = ts.padc[2] = 0.0;
     if (ts.kind == K_WEIERSTRASS) ts.padc[0] = -npad * (2.0 - 9.5367431640625e-07);
     if (ts.kind == K_ACKLEY) ts.padc[1] = npad;
+    if (ts.kind == K_HAPPYCAT) ts.padc[0] = -npad;
     if (ts.kind == K_LUNACEK) {
       ts.padc[0] = 6.25 * npad;
       ts.padc[1] = 6.25 * npad;
