@@ -92,9 +92,9 @@ int prepare_entry(Entry &e) {
     if (!err.empty()) return fail(CUROB_E_ARG, "%s", err.c_str());
     return hip_fail(he, "uploading composite tables");
   }
-  size_t pb = 0, zb = 0, gb = 0;
-  composite_scratch_needs(e.comp, pb, zb, gb);
-  he = g_ctx.scratch.reserve(pb, zb, gb);
+  size_t pb = 0, zb = 0, gb = 0, kb = 0;
+  composite_scratch_needs(e.comp, pb, zb, gb, kb);
+  he = g_ctx.scratch.reserve(pb, zb, gb, kb);
   if (he != hipSuccess) return hip_fail(he, "allocating scratch");
   return CUROB_OK;
 }

@@ -8,21 +8,21 @@
 
 namespace curob {
 
-hipError_t launch_tiled_split(int, const TiledProb &, const void *, void *, int, void *, void *, hipStream_t);
-hipError_t launch_tiled_split6(int, const TiledProb &, const void *, void *, int, void *, void *, hipStream_t);
-hipError_t launch_tiled_f32(int, const TiledProb &, const void *, void *, int, void *, void *, hipStream_t);
-hipError_t launch_tiled_f64(int, const TiledProb &, const void *, void *, int, void *, void *, hipStream_t);
+hipError_t launch_tiled_split(int, const TiledProb &, const void *, void *, int, void *, void *, void *, hipStream_t);
+hipError_t launch_tiled_split6(int, const TiledProb &, const void *, void *, int, void *, void *, void *, hipStream_t);
+hipError_t launch_tiled_f32(int, const TiledProb &, const void *, void *, int, void *, void *, void *, hipStream_t);
+hipError_t launch_tiled_f64(int, const TiledProb &, const void *, void *, int, void *, void *, void *, hipStream_t);
 hipError_t launch_blend(bool f64, const void *x, int n, int D, int nc, const double *o, const double *sigma,
                         const double *lambda, const double *bias, const void *G, int gstride, double fopt, void *out,
                         hipStream_t st);
 
 hipError_t launch_tiled(int path, int kind_hint, const TiledProb &tp, const void *x, void *out, int n, void *partials,
-                        void *zbuf, hipStream_t st) {
+                        void *zbuf, void *pack, hipStream_t st) {
   switch (path) {
-    case PATH_SPLIT: return launch_tiled_split(kind_hint, tp, x, out, n, partials, zbuf, st);
-    case PATH_SPLIT6: return launch_tiled_split6(kind_hint, tp, x, out, n, partials, zbuf, st);
-    case PATH_F32: return launch_tiled_f32(kind_hint, tp, x, out, n, partials, zbuf, st);
-    case PATH_F64: return launch_tiled_f64(kind_hint, tp, x, out, n, partials, zbuf, st);
+    case PATH_SPLIT: return launch_tiled_split(kind_hint, tp, x, out, n, partials, zbuf, pack, st);
+    case PATH_SPLIT6: return launch_tiled_split6(kind_hint, tp, x, out, n, partials, zbuf, pack, st);
+    case PATH_F32: return launch_tiled_f32(kind_hint, tp, x, out, n, partials, zbuf, pack, st);
+    case PATH_F64: return launch_tiled_f64(kind_hint, tp, x, out, n, partials, zbuf, pack, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -39,7 +39,7 @@ void CompositeDev::release() {
   ready = false;
 }
 
-hipError_t CompositeScratch::reserve(size_t pb, size_t zb, size_t gb) {
+hipError_t CompositeScratch::reserve(size_t pb, size_t zb, size_t gb, size_t kb) {
   auto grow = [](void *&ptr, size_t &have, size_t want) -> hipError_t {
     if (want <= have) return hipSuccess;
     if (ptr) (void)hipFree(ptr);
@@ -52,6 +52,7 @@ hipError_t CompositeScratch::reserve(size_t pb, size_t zb, size_t gb) {
   hipError_t e = grow(partials, partials_bytes, pb);
   if (e == hipSuccess) e = grow(zbuf, zbuf_bytes, zb);
   if (e == hipSuccess) e = grow(gbuf, gbuf_bytes, gb);
+  if (e == hipSuccess) e = grow(pack, pack_bytes, kb);
   return e;
 }
 
@@ -59,6 +60,7 @@ void CompositeScratch::release() {
   if (partials) (void)hipFree(partials);
   if (zbuf) (void)hipFree(zbuf);
   if (gbuf) (void)hipFree(gbuf);
+  if (pack) (void)hipFree(pack);
   *this = CompositeScratch{};
 }
 
@@ -138,13 +140,14 @@ hipError_t build_composite(const Problem &p, CompositeDev &cd, std::string &err)
   return hipSuccess;
 }
 
-void composite_scratch_needs(const CompositeDev &cd, size_t &pb, size_t &zb, size_t &gb) {
-  pb = zb = gb = 0;
+void composite_scratch_needs(const CompositeDev &cd, size_t &pb, size_t &zb, size_t &gb, size_t &kb) {
+  pb = zb = gb = kb = 0;
   auto acc_tiled = [&](const TiledDev (&t)[PATH_COUNT]) {
     for (int path = 0; path < PATH_COUNT; ++path)
       if (t[path].ready) {
         pb = std::max(pb, tiled_partials_bytes(t[path].tp, path));
         zb = std::max(zb, tiled_z_bytes(t[path].tp, path));
+        kb = std::max(kb, tiled_pack_bytes(t[path].tp, path));
       }
   };
   if (!cd.ready) return;
@@ -167,7 +170,7 @@ hipError_t launch_composite(int path, bool split_auto, const CompositeDev &cd, c
     unsigned char *oc = static_cast<unsigned char *>(out) + static_cast<size_t>(c0) * esz;
     hipError_t e;
     if (!cd.is_composition) {
-      e = launch_tiled(path, cd.kind_hint, cd.tiled[path].tp, xc, oc, ch, sc.partials, sc.zbuf, st);
+      e = launch_tiled(path, cd.kind_hint, cd.tiled[path].tp, xc, oc, ch, sc.partials, sc.zbuf, sc.pack, st);
       if (e != hipSuccess) return e;
       continue;
     }
@@ -182,7 +185,7 @@ hipError_t launch_composite(int path, bool split_auto, const CompositeDev &cd, c
         e = launch_resident(cp, pb, xc, gi, ch, resident_shape(cp, pb, ch, num_cu), st);
       } else {
         const int hint = cc.tiled[cp].tp.nsegs == 1 ? cc.tiled[cp].tp.segs[0].kind : -1;
-        e = launch_tiled(cp, hint, cc.tiled[cp].tp, xc, gi, ch, sc.partials, sc.zbuf, st);
+        e = launch_tiled(cp, hint, cc.tiled[cp].tp, xc, gi, ch, sc.partials, sc.zbuf, sc.pack, st);
       }
       if (e != hipSuccess) return e;
     }

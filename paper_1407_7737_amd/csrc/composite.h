@@ -39,8 +39,9 @@ struct CompositeScratch {
   void *partials = nullptr;
   void *zbuf = nullptr;
   void *gbuf = nullptr;
-  size_t partials_bytes = 0, zbuf_bytes = 0, gbuf_bytes = 0;
-  hipError_t reserve(size_t pb, size_t zb, size_t gb);
+  void *pack = nullptr;
+  size_t partials_bytes = 0, zbuf_bytes = 0, gbuf_bytes = 0, pack_bytes = 0;
+  hipError_t reserve(size_t pb, size_t zb, size_t gb, size_t kb);
   void release();
 };
 
@@ -49,7 +50,7 @@ struct CompositeScratch {
 hipError_t build_composite(const Problem &p, CompositeDev &cd, std::string &err);
 
 // Scratch sizes the problem needs.
-void composite_scratch_needs(const CompositeDev &cd, size_t &pb, size_t &zb, size_t &gb);
+void composite_scratch_needs(const CompositeDev &cd, size_t &pb, size_t &zb, size_t &gb, size_t &kb);
 
 // Evaluates n rows of x into out.  path is the arithmetic of the call; in split mode
 // (split_auto) the components of a composition pick three or six products per formula.

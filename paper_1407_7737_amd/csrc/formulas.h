@@ -230,6 +230,9 @@ __device__ __forceinline__ T finalize(const T (&s)[3], T p, int n) {
   }
 }
 
+// Pairwise families whose last term pairs z_n with z_1 (device-side copy of the host rule).
+__host__ __device__ constexpr bool kind_pair_wraps_c(int kind) { return kind == K_GRIEROSEN || kind == K_F6; }
+
 // Parameter passed to phi for each family.
 template <int KIND, typename T>
 __device__ __forceinline__ T kind_param(int n, double kparam) {

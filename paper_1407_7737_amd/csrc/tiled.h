@@ -18,12 +18,15 @@
 
 namespace curob {
 
-constexpr int kTileRows = 64;      // population rows per workgroup tile
+constexpr int kRowTiles = 8;                    // 16-row MFMA column blocks per workgroup tile
+constexpr int kTileRows = 16 * kRowTiles;       // population rows per workgroup tile
 constexpr int kTileK = 32;         // packed positions staged per k step
 constexpr int kGroupMTiles = 4;    // m-tiles (of 16 outputs) per workgroup, one per wave
 constexpr int kPartialSlots = 8;   // per (row, output group): s0 c0 s1 c1 s2 c2 product pad
 constexpr int kMaxSegments = 16;   // formula segments per tiled problem
 constexpr int kChunkRows = 65536;  // rows per pass (bounds the scratch buffers)
+constexpr int kPackLdsBytes = 150 * 1024;  // LDS budget of a pack workgroup
+constexpr int kNumXcd = 8;                 // accelerator complex dies the workgroups are dealt to
 
 struct TiledSeg {
   int kind;      // formula family of the segment
@@ -53,6 +56,8 @@ struct TiledProb {
   const int4 *groups;   // per output group: block, first m-tile, m-tile count, segment
   int D, Dp, nblocks, ngroups, nsegs;
   int any_pairwise;
+  int rowwise;    // unrotated basic problem: z = s (x - o) + c' per variable, no MFMA work
+  double scale0;  // s of that problem
   double bias;
   TiledSeg segs[kMaxSegments];
 };
@@ -67,12 +72,14 @@ struct TiledDev {
 // Builds and uploads the tiled tables of a basic or hybrid problem for one path.
 hipError_t build_tiled(const Problem &p, int path, TiledDev &td, std::string &err);
 
-// Scratch the tiled kernels need for one chunk of rows: partial sums and (pairwise) z.
+// Scratch the tiled kernels need for one chunk of rows: partial sums, (pairwise) z and the
+// packed B operands (bytes per packed position and row: 2 per bf16 term, 4 FP32, 8 FP64).
 size_t tiled_partials_bytes(const TiledProb &tp, int path);
 size_t tiled_z_bytes(const TiledProb &tp, int path);
+size_t tiled_pack_bytes(const TiledProb &tp, int path);
 
 // Evaluates rows [0, n) of x (n <= kChunkRows) into out using the scratch buffers.
 hipError_t launch_tiled(int path, int kind_hint, const TiledProb &tp, const void *x, void *out, int n, void *partials,
-                        void *zbuf, hipStream_t st);
+                        void *zbuf, void *pack, hipStream_t st);
 
 }  // namespace curob

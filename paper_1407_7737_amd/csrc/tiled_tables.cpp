@@ -192,6 +192,10 @@ hipError_t build_tiled(const Problem &p, int path, TiledDev &td, std::string &er
   tp.nsegs = nseg;
   tp.bias = p.fopt;
   tp.any_pairwise = 0;
+  // unrotated basic problems: the identity blocks of 32 keep packed position = variable, and
+  // the row-wise kernel reads the per-position tables by variable
+  tp.rowwise = (!hybrid && !rotate) ? 1 : 0;
+  tp.scale0 = s0.s;
   for (int sgi = 0; sgi < nseg; ++sgi) {
     const Segment &sg = p.segs[sgi];
     TiledSeg &ts = tp.segs[sgi];
@@ -253,6 +257,11 @@ hipError_t build_tiled(const Problem &p, int path, TiledDev &td, std::string &er
 size_t tiled_partials_bytes(const TiledProb &tp, int path) {
   const size_t esz = path == PATH_F64 ? 8 : 4;
   return static_cast<size_t>(tp.ngroups) * kChunkRows * kPartialSlots * esz;
+}
+
+size_t tiled_pack_bytes(const TiledProb &tp, int path) {
+  const size_t bpp = is_split(path) ? 2 * split_terms(path) : (path == PATH_F64 ? 8 : 4);
+  return static_cast<size_t>(kChunkRows) * tp.Dp * bpp;
 }
 
 size_t tiled_z_bytes(const TiledProb &tp, int path) {
