@@ -357,15 +357,27 @@ __device__ __forceinline__ void resident_eval(const DevProb &pb, const typename 
 #pragma unroll
     for (int b = 0; b < NB; ++b) a[b].init();
 
+    // rotated: the MFMAs of m-tile m + 1 are issued before the formula work of m-tile m, so
+    // the matrix cores and the vector ALUs overlap within the wave
+    Acc4 acc_cur[NB], acc_nxt[NB];
+    if constexpr (ROT) mtile<P>(acc_cur, mtab[0], bf, s_q, lane);
     for (int m = 0; m < MT; ++m) {
       T z[NB][4];
       if constexpr (ROT) {
-        Acc4 acc[NB];
-        mtile<P>(acc, mtab[m], bf, s_q, lane);
+        if (m + 1 < MT) mtile<P>(acc_nxt, mtab[m + 1], bf, s_q, lane);
+        T c4[4];
+        if constexpr (P == PATH_F64) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) c4[e] = s_cz[frag_pos<P, ROT>(m, q, e)];
+        } else {
+          read4(c4, s_cz, 16 * m + 4 * q);
+        }
 #pragma unroll
         for (int b = 0; b < NB; ++b)
 #pragma unroll
-          for (int e = 0; e < 4; ++e) z[b][e] = T(acc[b][e]) + s_cz[frag_pos<P, ROT>(m, q, e)];
+          for (int e = 0; e < 4; ++e) z[b][e] = T(acc_cur[b][e]) + c4[e];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc_cur[b] = acc_nxt[b];
       } else {
         T c4[4];
         read4(c4, s_cz, 16 * m + 4 * q);

@@ -77,21 +77,34 @@ __device__ __forceinline__ T t_abs(T v) {
   if constexpr (sizeof(T) == 4) return __builtin_fabsf(v); else return __builtin_fabs(v);
 }
 
-// Modified Schwefel g1 of Eq. (basic_schwefel), branch free.  With a = |w|: for a <= 500 the
-// value is w sin(sqrt a); beyond, both outer branches fold a back to u = 500 - mod(a, 500)
-// and subtract (a - 500)^2 / (10000 n): g1 = sign(w) u sin(sqrt u) - penalty.
+// Modified Schwefel g1 of Eq. (basic_schwefel), branch free, on w = z + 420.9687... (the
+// tables fold the constant into c').  With a = |w|: for a <= 500 the value is w sin(sqrt a);
+// beyond, both outer branches fold a back to u = 500 - mod(a, 500) and subtract
+// (a - 500)^2 / (10000 n): g1 = sign(w) u sin(sqrt u) - penalty.
 template <typename T>
 __device__ __forceinline__ T schwefel_g1(T w, T inv10000n) {
   const T a = t_abs(w);
-  T m = a - T(500) * t_floor(a * T(0.002));  // mod(a, 500); the floor may be off by one
-  m = m < T(0) ? m + T(500) : m;
-  m = m >= T(500) ? m - T(500) : m;
   const bool far = a > T(500);
-  const T u = far ? T(500) - m : a;
-  const T d = a - T(500);
-  const T pen = far ? d * d * inv10000n : T(0);
-  const T g = u * sin_rad(t_sqrt(u));
-  return (w < T(0) ? -g : g) - pen;
+  if constexpr (sizeof(T) == 4) {
+    // mod(a, 500) as 500 fract(a / 500): a few ulps of a from the exact remainder, which
+    // only moves the jumps at a = 1000, 1500, ... by as much
+    const float m = 500.0f * __builtin_amdgcn_fractf(a * 0.002f);
+    const float u = far ? 500.0f - m : a;
+    const float d = __builtin_fmaxf(a - 500.0f, 0.0f);
+    // sqrt(u) <= sqrt(500) < 23: the sine's argument in revolutions stays below 4, inside
+    // the hardware sine's domain, so no range reduction is needed
+    const float sn = __builtin_amdgcn_sinf(__builtin_sqrtf(u) * 0.15915494309189535f);
+    return __builtin_copysignf(u, w) * sn - d * d * inv10000n;
+  } else {
+    T m = a - T(500) * t_floor(a * T(0.002));  // mod(a, 500); the floor may be off by one
+    m = m < T(0) ? m + T(500) : m;
+    m = m >= T(500) ? m - T(500) : m;
+    const T u = far ? T(500) - m : a;
+    const T d = a - T(500);
+    const T pen = far ? d * d * inv10000n : T(0);
+    const T g = u * sin_rad(t_sqrt(u));
+    return (w < T(0) ? -g : g) - pen;
+  }
 }
 
 template <int KIND>
@@ -154,7 +167,7 @@ __device__ __forceinline__ void phi(T (&v)[3], T &p, T z, T zn, T coef, T prm) {
     const T e = z - T(1);
     v[0] += T(100) * d * d + e * e;
   } else if constexpr (KIND == K_SCHWEFEL) {
-    v[0] += schwefel_g1(z + T(420.9687462275036), prm);
+    v[0] += schwefel_g1(z, prm);  // z carries the 420.9687... offset
   } else if constexpr (KIND == K_KATSUURA) {
     T t = T(0), pj = T(1);
 #pragma unroll 4

@@ -110,14 +110,14 @@ bool build_host_tables(const Problem &p, int path, HostTables &ht, std::string &
   ht.goff.assign(pad16(KT * KW * 2) / 2, static_cast<uint16_t>(D * esz));
   for (int pp = 0; pp < D; ++pp) ht.goff[pp] = static_cast<uint16_t>(order[pp] * esz);
   // per packed position: c' = c - s (Q o_lo)_p, coefficient, formula successor.  Padding gets
-  // z = 0 (Schwefel: z = -420.97..., where g1 vanishes) and neutral coefficients.
+  // z = 0 and neutral coefficients.  Schwefel's g1 takes z + 420.9687..., folded into c' (its
+  // padding then gives w = 0, where g1 vanishes).
   ht.cz.assign(pad16(Mp * esz), 0);
   ht.coef.assign(pad16(Mp * esz), 0);
   ht.succ.assign(pad16(Mp * 2) / 2, static_cast<int16_t>(-1));
   const bool pair = kind_is_pairwise(kind), wraps = kind_pair_wraps(kind);
   for (int pp = 0; pp < Mp; ++pp) {
     if (pp >= D) {
-      if (kind == K_SCHWEFEL) store(ht.cz, pp, -420.9687462275036);
       if (kind == K_POWERS) store(ht.coef, pp, 2.0);
       continue;
     }
@@ -129,7 +129,7 @@ bool build_host_tables(const Problem &p, int path, HostTables &ht, std::string &
     } else {
       corr = s * olo[i];
     }
-    store(ht.cz, pp, c - corr);
+    store(ht.cz, pp, c - corr + (kind == K_SCHWEFEL ? 420.9687462275036 : 0.0));
     double cf = formula_coef(base, i, D);
     if (kind == K_GRIEWANK && !f64) cf /= 2.0 * M_PI;  // FP32 cosine takes revolutions
     store(ht.coef, pp, cf);

@@ -105,7 +105,6 @@ hipError_t build_tiled(const Problem &p, int path, TiledDev &td, std::string &er
     for (int a = 0; a < ceil32(B.n); ++a) {
       const int pp = poff[b] + a;
       if (a >= B.n) {
-        if (kind == K_SCHWEFEL) store(cz, pp, -420.9687462275036);
         if (kind == K_POWERS) store(coef, pp, 2.0);
         continue;
       }
@@ -115,7 +114,8 @@ hipError_t build_tiled(const Problem &p, int path, TiledDev &td, std::string &er
         const double qv = B.Q ? (*B.Q)[static_cast<size_t>(a) * B.n + c] : (a == c ? 1.0 : 0.0);
         corr += qv * olo[orig[B.off + c]];
       }
-      store(cz, pp, sg.c - B.s * corr);
+      // Schwefel's g1 takes z + 420.9687..., folded into c' (padding gives w = 0, g1 = 0)
+      store(cz, pp, sg.c - B.s * corr + (kind == K_SCHWEFEL ? 420.9687462275036 : 0.0));
       const int n_f = hybrid ? sg.n : D;
       double cf = formula_coef(sg.base, idx_in_seg[pp], n_f);
       if (kind == K_GRIEWANK && !f64) cf /= 2.0 * M_PI;

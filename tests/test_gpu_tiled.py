@@ -257,3 +257,58 @@ def test_tiled_scratch_reuse_and_chunking(env):
         p = orc.basic(fid, 200, SEED)
         f = c.func_evaluate(fid, torch.from_numpy(x).cuda()).cpu().numpy()
         assert rel_err(f[rows], p(x[rows])).max() <= TOL64, fid
+
+
+STAR = [0, 2, 9, 10, 11, 14, 16, 19]
+
+
+@pytest.mark.parametrize("dim", [30, 50])
+def test_scale_workload_n65536(env, dim):
+    """The scale workload (D in {30, 50}, N = 65536, FP64 and FP32 paths) on the eight
+    rotated/unrotated formulas: every row of the FP64 path, 4096 sampled rows of the split and
+    FP32 paths against the oracle."""
+    c, orc, torch, use = env
+    use(dim, maxc=65536)
+    from paper_1407_7737_amd.inputs import population
+    n = 65536
+    x64 = population(n, dim, seed=11)
+    x32 = x64.astype(np.float32)
+    rows = np.r_[0:64, np.linspace(64, n - 1, 4032).astype(int)]
+    for fid in STAR:
+        say(f"[scale] dim={dim} fid={fid}")
+        p = orc.basic(fid, dim, SEED)
+        f64 = c.func_evaluate(fid, torch.from_numpy(x64).cuda()).cpu().numpy()
+        assert rel_err(f64, p(x64, threads=16)).max() <= TOL64, fid
+        x32w = x32[rows].astype(np.float64)
+        ref32 = p(x32w, threads=16)
+        allow = basic_allowance(orc, fid, p.shift(), p.rotation(), x32w)
+        for m in (c.MODE_SPLIT, c.MODE_FP32):
+            c.set_mode(m)
+            f = c.func_evaluatef(fid, torch.from_numpy(x32).cuda()).cpu().numpy()
+            check32(f[rows], ref32, allow, (m, dim, fid))
+        c.set_mode(c.MODE_SPLIT)
+
+
+def test_precision_workload_d1000_n262144(env):
+    """The precision workload at D = 1000, N = 2^18 in the launch configuration the bench times
+    (default split mode, four 65536-row passes): 2048 sampled rows per formula, spread over
+    every pass, against the oracle; the FP64 path on the same rows."""
+    c, orc, torch, use = env
+    n = 1 << 18
+    use(1000, maxc=n)
+    from paper_1407_7737_amd.inputs import population
+    x32 = population(n, 1000, seed=0, dtype=np.float32)
+    rows = np.r_[0:32, 65504:65568, np.linspace(32, n - 1, 1952).astype(int)]
+    dx32 = torch.from_numpy(x32).cuda()
+    x32w = x32[rows].astype(np.float64)
+    for fid in STAR:
+        say(f"[precision] fid={fid}")
+        p = orc.basic(fid, 1000, SEED)
+        f = c.func_evaluatef(fid, dx32).cpu().numpy()
+        ref32 = p(x32w, threads=16)
+        allow = basic_allowance(orc, fid, p.shift(), p.rotation(), x32w)
+        e = check32(f[rows], ref32, allow, ("split", fid))
+        f64 = c.func_evaluate(fid, torch.from_numpy(x32w).cuda()).cpu().numpy()
+        e64 = rel_err(f64, ref32).max()
+        say(f"[precision] fid={fid} split max rel err {e:.2e}, fp64 {e64:.2e}")
+        assert e64 <= TOL64, fid
