@@ -359,12 +359,18 @@ __device__ __forceinline__ void resident_eval(const DevProb &pb, const typename 
 
     // rotated: the MFMAs of m-tile m + 1 are issued before the formula work of m-tile m, so
     // the matrix cores and the vector ALUs overlap within the wave
+    // (not on the FP64 path, whose doubled accumulators would not fit the registers)
+    constexpr bool PIPE = P != PATH_F64;
     Acc4 acc_cur[NB], acc_nxt[NB];
-    if constexpr (ROT) mtile<P>(acc_cur, mtab[0], bf, s_q, lane);
+    if constexpr (ROT && PIPE) mtile<P>(acc_cur, mtab[0], bf, s_q, lane);
     for (int m = 0; m < MT; ++m) {
       T z[NB][4];
       if constexpr (ROT) {
-        if (m + 1 < MT) mtile<P>(acc_nxt, mtab[m + 1], bf, s_q, lane);
+        if constexpr (PIPE) {
+          if (m + 1 < MT) mtile<P>(acc_nxt, mtab[m + 1], bf, s_q, lane);
+        } else {
+          mtile<P>(acc_cur, mtab[m], bf, s_q, lane);
+        }
         T c4[4];
         if constexpr (P == PATH_F64) {
 #pragma unroll
@@ -376,8 +382,10 @@ __device__ __forceinline__ void resident_eval(const DevProb &pb, const typename 
         for (int b = 0; b < NB; ++b)
 #pragma unroll
           for (int e = 0; e < 4; ++e) z[b][e] = T(acc_cur[b][e]) + c4[e];
+        if constexpr (PIPE) {
 #pragma unroll
-        for (int b = 0; b < NB; ++b) acc_cur[b] = acc_nxt[b];
+          for (int b = 0; b < NB; ++b) acc_cur[b] = acc_nxt[b];
+        }
       } else {
         T c4[4];
         read4(c4, s_cz, 16 * m + 4 * q);
@@ -411,7 +419,7 @@ __device__ __forceinline__ void resident_eval(const DevProb &pb, const typename 
 #pragma unroll
           for (int e = 0; e < 4; ++e) phi<KIND, T>(v, a[b].p, z[b][e], T(0), cf[e], prm);
 #pragma unroll
-          for (int k = 0; k < KT_::nsum; ++k) a[b].add(k, v[k]);
+          for (int k = 0; k < KT_::nsum; ++k) acc_add<KIND, T>(a[b], k, v[k]);
         }
       }
     }
@@ -431,7 +439,7 @@ __device__ __forceinline__ void resident_eval(const DevProb &pb, const typename 
             phi<KIND, T>(w, a[b].p, zr[p], zr[sp < 0 ? p : sp], T(0), prm);
             v[0] += sp < 0 ? T(0) : w[0];
           }
-          a[b].add(0, v[0]);
+          acc_add<KIND, T>(a[b], 0, v[0]);
         }
       }
     }

@@ -132,7 +132,7 @@ __device__ __forceinline__ void reduce_tile(const typename Types<P>::Acc4 (&acc)
 #pragma unroll
     for (int e = 0; e < 4; ++e) phi<K, T>(v, a.p, T(acc[cb][e]) + zc[e], T(0), cf[e], prm);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) a.add(k, v[k]);
+    for (int k = 0; k < 3; ++k) acc_add<K, T>(a, k, v[k]);
 #pragma unroll
     for (int sh = 16; sh <= 32; sh <<= 1) {
 #pragma unroll
@@ -575,7 +575,7 @@ __global__ __launch_bounds__(256) void k_rowwise(TiledProb tp, const typename Ty
       }
     }
 #pragma unroll
-    for (int k = 0; k < 3; ++k) a.add(k, v[k]);
+    for (int k = 0; k < 3; ++k) acc_add<KIND, T>(a, k, v[k]);
   }
 #pragma unroll
   for (int sh = 1; sh < 64; sh <<= 1) {

@@ -113,12 +113,23 @@ struct KindTraits {
   static constexpr bool needs_coef = KIND == K_WSPHERE || KIND == K_POWERS || KIND == K_SHARPV ||
                                      KIND == K_GRIEWANK || KIND == K_KATSUURA;
   static constexpr bool has_product = KIND == K_GRIEWANK || KIND == K_KATSUURA;
+  // Sums whose terms can cancel (mixed signs) are Kahan-compensated in FP32; sums of
+  // non-negative terms are added plainly: their relative error stays below (terms) x 2^-24.
+  static constexpr bool kahan = KIND == K_WEIERSTRASS || KIND == K_SCHWEFEL || KIND == K_ACKLEY ||
+                                KIND == K_LUNACEK || KIND == K_HAPPYCAT || KIND == K_HGBAT;
   // sums the family keeps per row
   static constexpr int nsum = (KIND == K_LUNACEK) ? 3
                               : (KIND == K_SHARPV || KIND == K_ACKLEY || KIND == K_HAPPYCAT || KIND == K_HGBAT) ? 2
                               : (KIND == K_KATSUURA) ? 0
                                                      : 1;
 };
+
+// Adds a group sum to a row sum: compensated where the family's sums can cancel.
+template <int KIND, typename T>
+__device__ __forceinline__ void acc_add(Acc<T> &a, int k, T v) {
+  if constexpr (KindTraits<KIND>::kahan) a.add(k, v);
+  else a.s[k] += v;
+}
 
 // Adds the term(s) of one element z (with its formula successor zn for the pairwise
 // families) to the group sums v[] and the product p.  `prm` carries the row-independent
