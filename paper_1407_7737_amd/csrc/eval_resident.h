@@ -269,6 +269,39 @@ __device__ __forceinline__ void mtile(typename PathT<P>::Acc4 (&acc)[blocks_of(P
   }
 }
 
+// One m-tile on the 4-wide paths (FP32 and FP64 MFMA) with B read from the staged rows inside
+// a runtime loop over the m-tile's k range: no per-k-tile branches over the full 32-tile
+// range and no register-resident B, so more waves fit.  Two accumulators halve the dependent
+// chain of MFMAs.
+template <int P>
+__device__ __forceinline__ void mtile_stream(typename PathT<P>::Acc4 (&acc)[1], int4 mi, const uint16_t *s_goff,
+                                             const unsigned char *Yb, const unsigned char *s_q, int lane, int q) {
+  using Frag = typename RotOps<P>::Frag;
+  using Acc4 = typename PathT<P>::Acc4;
+  Acc4 a0 = Acc4{0, 0, 0, 0}, a1 = Acc4{0, 0, 0, 0};
+  const Frag *qa = reinterpret_cast<const Frag *>(s_q) + (mi.z - mi.x) * 64 + lane;
+  int kt = mi.x;
+  for (; kt < mi.y; kt += 2) {
+    const Frag b0 = *reinterpret_cast<const Frag *>(Yb + s_goff[kt * 4 + q]);
+    const Frag b1 = *reinterpret_cast<const Frag *>(Yb + s_goff[kt * 4 + 4 + q]);
+    if constexpr (P == PATH_F64) {
+      a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[kt * 64], b0, a0, 0, 0, 0);
+      a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[kt * 64 + 64], b1, a1, 0, 0, 0);
+    } else {
+      a0 = __builtin_amdgcn_mfma_f32_16x16x4f32(qa[kt * 64], b0, a0, 0, 0, 0);
+      a1 = __builtin_amdgcn_mfma_f32_16x16x4f32(qa[kt * 64 + 64], b1, a1, 0, 0, 0);
+    }
+  }
+  if (kt == mi.y) {
+    const Frag b0 = *reinterpret_cast<const Frag *>(Yb + s_goff[kt * 4 + q]);
+    if constexpr (P == PATH_F64)
+      a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[kt * 64], b0, a0, 0, 0, 0);
+    else
+      a0 = __builtin_amdgcn_mfma_f32_16x16x4f32(qa[kt * 64], b0, a0, 0, 0, 0);
+  }
+  acc[0] = a0 + a1;
+}
+
 // The four packed positions frag_pos(m, q, 0..3) of a row as one vector from LDS (unrotated
 // layout: consecutive, 16-byte aligned because S and 16 m + 4 q are multiples of 4).
 template <typename T>
@@ -347,11 +380,17 @@ __device__ __forceinline__ void resident_eval(const DevProb &pb, const typename 
     if (gn < gend) xt.load(rows_rsrc(x, gn * ROWS, n, D), nload, lane);
     wave_sync();
 
+    // 4-wide paths without pairwise z exchange read B from the rows in the m-tile loop
+    constexpr bool SB = ROT && !is_split(P) && !KT_::pairwise && NB == 1;
     typename R::Frag bf[R::NTERM][NB][R::KTMAX];
-    if constexpr (ROT) {
+    if constexpr (ROT && !SB) {
       gather_b<P>(bf, pb.KT, s_goff, Yb, bstride, q);
       if constexpr (KT_::pairwise) wave_sync();  // the rows are overwritten with z below
     }
+    auto rotate_m = [&](Acc4 (&acc)[NB], int mm) {
+      if constexpr (SB) mtile_stream<P>(acc, mtab[mm], s_goff, Yb, s_q, lane, q);
+      else mtile<P>(acc, mtab[mm], bf, s_q, lane);
+    };
 
     Acc<T> a[NB];
 #pragma unroll
@@ -362,14 +401,14 @@ __device__ __forceinline__ void resident_eval(const DevProb &pb, const typename 
     // (not on the FP64 path, whose doubled accumulators would not fit the registers)
     constexpr bool PIPE = P != PATH_F64;
     Acc4 acc_cur[NB], acc_nxt[NB];
-    if constexpr (ROT && PIPE) mtile<P>(acc_cur, mtab[0], bf, s_q, lane);
+    if constexpr (ROT && PIPE) rotate_m(acc_cur, 0);
     for (int m = 0; m < MT; ++m) {
       T z[NB][4];
       if constexpr (ROT) {
         if constexpr (PIPE) {
-          if (m + 1 < MT) mtile<P>(acc_nxt, mtab[m + 1], bf, s_q, lane);
+          if (m + 1 < MT) rotate_m(acc_nxt, m + 1);
         } else {
-          mtile<P>(acc_cur, mtab[m], bf, s_q, lane);
+          rotate_m(acc_cur, m);
         }
         T c4[4];
         if constexpr (P == PATH_F64) {
