@@ -158,7 +158,7 @@ __device__ __forceinline__ void reduce_tile(const typename Types<P>::Acc4 (&acc)
 // Pack chunk of row tile rt, global k step c: chunk index rt * nsteps + c.
 template <int P>
 __global__ __launch_bounds__(256) void k_tiled_pack(TiledProb tp, const typename Types<P>::T *__restrict__ x, int n,
-                                                    int rows_per_wg, int vec, unsigned char *__restrict__ pack) {
+                                                    int rows_per_wg, int SX, int vec, unsigned char *__restrict__ pack) {
   using T = typename Types<P>::T;
   constexpr int NP = pack_parts<P>();
   extern __shared__ __align__(16) unsigned char smem[];
@@ -171,17 +171,16 @@ __global__ __launch_bounds__(256) void k_tiled_pack(TiledProb tp, const typename
   const int nvalid = n - row0 < 0 ? 0 : (n - row0 < R ? n - row0 : R);
   for (int i = threadIdx.x; i < tp.Dp; i += 256) s_gidx[i] = tp.gidx[i];
   for (int i = threadIdx.x; i < D; i += 256) s_oh[i] = reinterpret_cast<const T *>(tp.oh)[i];
-  // stage the rows: batches of independent loads per thread keep many requests in flight
-  constexpr int U = 8;
+  // stage the rows at stride SX (the 16 rows of a tile fall in distinct LDS banks); all of a
+  // thread's loads are issued before any store so many requests are in flight
+  constexpr int U = 16;
   const T *xs = x + static_cast<size_t>(row0) * D;
-  const int total = R * D, valid = nvalid * D;
   if (vec) {
     // rows of 16-byte multiples, 16-byte aligned: vector loads
     constexpr int NV = 16 / static_cast<int>(sizeof(T));
     using V = typename std::conditional<sizeof(T) == 8, f64x2, f32x4>::type;
     const V *xv = reinterpret_cast<const V *>(xs);
-    V *sv = reinterpret_cast<V *>(s_x);
-    const int tv = total / NV, vv = valid / NV;
+    const int DV = D / NV, tv = R * DV, vv = nvalid * DV;
     for (int base = 0; base < tv; base += 256 * U) {
       V v[U];
 #pragma unroll
@@ -192,10 +191,14 @@ __global__ __launch_bounds__(256) void k_tiled_pack(TiledProb tp, const typename
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int i = base + 256 * u + threadIdx.x;
-        if (i < tv) sv[i] = v[u];
+        if (i < tv) {
+          const int row = i / DV;
+          *reinterpret_cast<V *>(s_x + row * SX + (i - row * DV) * NV) = v[u];
+        }
       }
     }
   } else {
+    const int total = R * D, valid = nvalid * D;
     for (int base = 0; base < total; base += 256 * U) {
       T v[U];
 #pragma unroll
@@ -206,7 +209,10 @@ __global__ __launch_bounds__(256) void k_tiled_pack(TiledProb tp, const typename
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int i = base + 256 * u + threadIdx.x;
-        if (i < total) s_x[i] = v[u];
+        if (i < total) {
+          const int row = i / D;
+          s_x[row * SX + (i - row * D)] = v[u];
+        }
       }
     }
   }
@@ -218,7 +224,7 @@ __global__ __launch_bounds__(256) void k_tiled_pack(TiledProb tp, const typename
     const int c = it / (4 * R), rem = it - c * (4 * R);
     const int g = rem / R, r = r0 + rem % R;
     const int lane = r + 16 * g;
-    const T *xr = s_x + (r - r0) * D;
+    const T *xr = s_x + (r - r0) * SX;
     const bool live = r - r0 < nvalid;
     unsigned char *dst = pack + (static_cast<size_t>(rt) * nsteps + c) * chunk_bytes<P>() + lane * 16;
     T y[8];
@@ -662,15 +668,31 @@ __global__ __launch_bounds__(256) void k_tiled_finalize(TiledProb tp, const type
   if (lane == 0) out[row] = F + T(tp.bias);
 }
 
-// Rows of one pack workgroup: the largest power of two <= 16 whose rows fit the LDS budget
-// next to the position tables; 0 when even one row does not fit.
+// Rows of one pack workgroup: the largest power of two <= 16 whose rows and position tables
+// fit a quarter of the LDS (four workgroups per CU overlap their load and store phases), or
+// the largest that fits the whole budget; 0 when even one row does not fit.
 template <int P>
-inline int pack_rows(const TiledProb &tp) {
+inline int pack_rows(const TiledProb &tp, int SX) {
   const int esz = P == PATH_F64 ? 8 : 4;
   const int fixed = round16(tp.Dp * 4) + round16(tp.D * esz);
   for (int R = 16; R >= 1; R >>= 1)
-    if (fixed + R * tp.D * esz <= kPackLdsBytes) return R;
+    if (fixed + R * SX * esz <= kMaxLdsBytes / 4) return R;
+  for (int R = 16; R >= 1; R >>= 1)
+    if (fixed + R * SX * esz <= kPackLdsBytes) return R;
   return 0;
+}
+
+// LDS row stride of the pack kernel (elements): >= D, a multiple of the vector width, and an
+// odd multiple of 4 banks from row to row, so the 16 rows of a tile hit distinct banks.
+template <int P>
+inline int pack_stride(int D) {
+  int sx = D;
+  if constexpr (P == PATH_F64) {
+    while (sx % 4 != 2) ++sx;  // 2 banks per element: 2 sx = 4 (mod 8)
+  } else {
+    while (sx % 8 != 4) ++sx;  // sx = 4 (mod 8)
+  }
+  return sx;
 }
 
 // pack, GEMM + formula, finalize for rows [0, n) (n <= kChunkRows) of one path
@@ -691,10 +713,11 @@ hipError_t launch_tiled_path(int kind_hint, const TiledProb &tp, const void *x, 
     void *args[] = {&arg, &xa, &na, &oa};
     return hipLaunchKernel(rowwise[kind_hint], dim3((n + 3) / 4), dim3(256), args, 0, st);
   }
-  const int R = pack_rows<P>(tp);
+  const int SX = pack_stride<P>(tp.D);
+  const int R = pack_rows<P>(tp, SX);
   if (R == 0) return hipErrorInvalidValue;
   const int esz = P == PATH_F64 ? 8 : 4;
-  const int lds = round16(tp.Dp * 4) + round16(tp.D * esz) + R * tp.D * esz;
+  const int lds = round16(tp.Dp * 4) + round16(tp.D * esz) + R * SX * esz;
   const void *pk = reinterpret_cast<const void *>(&k_tiled_pack<P>);
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(pk, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
@@ -706,9 +729,9 @@ hipError_t launch_tiled_path(int kind_hint, const TiledProb &tp, const void *x, 
   void *pa = partials, *za = zbuf, *oa = out;
   unsigned char *pka = static_cast<unsigned char *>(pack);
   const unsigned char *pkc = pka;
-  int na = n, Ra = R;
+  int na = n, Ra = R, SXa = SX;
   int va = ((tp.D * esz) % 16 == 0 && (reinterpret_cast<uintptr_t>(x) % 16) == 0) ? 1 : 0;
-  void *pargs[] = {&arg, &xa, &na, &Ra, &va, &pka};
+  void *pargs[] = {&arg, &xa, &na, &Ra, &SXa, &va, &pka};
   hipError_t e = hipLaunchKernel(pk, dim3(tiles * kTileRows / R), dim3(256), pargs, static_cast<size_t>(lds), st);
   if (e != hipSuccess) return e;
   int ta = tiles;
