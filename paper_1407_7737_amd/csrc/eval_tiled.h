@@ -64,7 +64,8 @@ __host__ __device__ constexpr int chunk_bytes() {
 // kGroupMTiles x kRowTiles: every B fragment read from LDS feeds kWaveM m-tiles.
 constexpr int kWaveM = 2;
 constexpr int kWaveR = 4;
-static_assert(kGroupMTiles / kWaveM * (kRowTiles / kWaveR) == 4, "four waves per workgroup");
+constexpr int kGemmWaves = kGroupMTiles / kWaveM * (kRowTiles / kWaveR);
+constexpr int kGemmThreads = 64 * kGemmWaves;
 
 template <int P>
 __device__ __forceinline__ int frag_pos(int q, int e) {
@@ -275,7 +276,7 @@ using AFragT = typename std::conditional<is_split(P), bf16x8, typename Types<P>:
 template <int P>
 constexpr int kNA = is_split(P) ? split_terms(P) : 8;  // A fragments per step
 template <int P>
-constexpr int kPT = kRowTiles * pack_parts<P>() / 4;    // 16-byte B pieces per thread per step
+constexpr int kPT = kRowTiles * pack_parts<P>() * 64 / kGemmThreads;  // 16-byte B pieces per thread per step
 
 // One k step of the GEMM: issue the loads of step c + 2 into (rl, au after use), run step c's
 // MFMAs from LDS buffer c & 1 with the rotation tiles au, store step c + 1 (rw) into the other
@@ -367,7 +368,7 @@ __device__ __forceinline__ void gemm_step(int c, int nst, const unsigned char *s
   __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int k2 = 0; k2 < PT; ++k2)
-    *reinterpret_cast<u32x4 *>(s_mem + (buf ^ 1) * BUF + (tid + 256 * k2) * 16) = rw[k2];
+    *reinterpret_cast<u32x4 *>(s_mem + (buf ^ 1) * BUF + (tid + kGemmThreads * k2) * 16) = rw[k2];
   __syncthreads();
 }
 
@@ -426,7 +427,7 @@ __device__ __forceinline__ void mtile_epilogue(const TiledProb &tp, const TiledS
 // KIND >= 0: one formula family for every segment (basic functions); KIND < 0: the family of
 // each output group's segment is read at run time (hybrids).
 template <int P, int KIND>
-__global__ __launch_bounds__(256) void k_tiled_gemm(TiledProb tp, const unsigned char *pack, int n,
+__global__ __launch_bounds__(kGemmThreads) void k_tiled_gemm(TiledProb tp, const unsigned char *pack, int n,
                                                     int ntiles, typename Types<P>::T *__restrict__ partials,
                                                     typename Types<P>::T *__restrict__ zbuf) {
   using T = typename Types<P>::T;
@@ -467,7 +468,7 @@ __global__ __launch_bounds__(256) void k_tiled_gemm(TiledProb tp, const unsigned
   size_t src_off[PT];
 #pragma unroll
   for (int k2 = 0; k2 < PT; ++k2) {
-    const int piece = tid + 256 * k2;
+    const int piece = tid + kGemmThreads * k2;
     const int i = piece / (NP * 64), off = piece - i * (NP * 64);
     src_off[k2] = static_cast<size_t>(i) * nsteps_all * CH + off * 16;
   }
@@ -501,7 +502,7 @@ __global__ __launch_bounds__(256) void k_tiled_gemm(TiledProb tp, const unsigned
       for (int u = 0; u < NA; ++u) a1[j][u] = qa[j][(NA + u) * 64];
   }
 #pragma unroll
-  for (int k2 = 0; k2 < PT; ++k2) *reinterpret_cast<u32x4 *>(s_mem + (tid + 256 * k2) * 16) = rb0[k2];
+  for (int k2 = 0; k2 < PT; ++k2) *reinterpret_cast<u32x4 *>(s_mem + (tid + kGemmThreads * k2) * 16) = rb0[k2];
   __syncthreads();
 
   Acc4 acc[kWaveM][kWaveR];
@@ -737,7 +738,7 @@ hipError_t launch_tiled_path(int kind_hint, const TiledProb &tp, const void *x, 
   int ta = tiles;
   void *gargs[] = {&arg, &pkc, &na, &ta, &pa, &za};
   const int rounds = (tiles + kNumXcd - 1) / kNumXcd;
-  e = hipLaunchKernel(fn, dim3(tp.ngroups * rounds * kNumXcd), dim3(256), gargs, 0, st);
+  e = hipLaunchKernel(fn, dim3(tp.ngroups * rounds * kNumXcd), dim3(kGemmThreads), gargs, 0, st);
   if (e != hipSuccess) return e;
   void *fargs[] = {&arg, &pa, &za, &na, &oa};
   return hipLaunchKernel(reinterpret_cast<const void *>(&k_tiled_finalize<P>), dim3((n + 3) / 4), dim3(256), fargs, 0,

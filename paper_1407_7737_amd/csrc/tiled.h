@@ -21,7 +21,7 @@ namespace curob {
 constexpr int kRowTiles = 8;                    // 16-row MFMA column blocks per workgroup tile
 constexpr int kTileRows = 16 * kRowTiles;       // population rows per workgroup tile
 constexpr int kTileK = 32;         // packed positions staged per k step
-constexpr int kGroupMTiles = 4;    // m-tiles (of 16 outputs) per workgroup, one per wave
+constexpr int kGroupMTiles = 8;    // m-tiles (of 16 outputs) per workgroup output group
 constexpr int kPartialSlots = 8;   // per (row, output group): s0 c0 s1 c1 s2 c2 product pad
 constexpr int kMaxSegments = 16;   // formula segments per tiled problem
 constexpr int kChunkRows = 65536;  // rows per pass (bounds the scratch buffers)
