@@ -187,7 +187,53 @@ def secondary(torch, c, reps: int = 10) -> dict:
         finally:
             c.dispose()
     out["batch_64"]["one_call_per_population_ms"] = per_call
+    out["latency_n50"] = latency_small(torch, c)
     return out
+
+
+def latency_small(torch, c, calls: int = 100) -> dict:
+    """The paper's own regime: many calls on 50 candidates (rotated Rastrigin, split path).
+    Per call: wall-clock of back-to-back eager calls (Python and launch included), the same
+    calls replayed from one captured graph, and the kernel alone (HIP events)."""
+    from paper_1407_7737_amd.inputs import population
+    res = {}
+    for d in (10, 32, 64, 96):
+        c.initialize(d, 64, 0)
+        try:
+            x = torch.from_numpy(population(50, d, seed=d, dtype=np.float32)).cuda()
+            o = torch.empty(50, device="cuda")
+            for _ in range(10):
+                c.func_evaluatef(11, x, out=o)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(calls):
+                c.func_evaluatef(11, x, out=o)
+            torch.cuda.synchronize()
+            eager = (time.perf_counter() - t0) / calls
+            g = torch.cuda.CUDAGraph()
+            s = torch.cuda.Stream()
+            s.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(s):
+                with torch.cuda.graph(g, stream=s):
+                    for _ in range(calls):
+                        c.func_evaluatef(11, x, out=o)
+            torch.cuda.current_stream().wait_stream(s)
+            g.replay()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(5):
+                g.replay()
+            torch.cuda.synchronize()
+            graph = (time.perf_counter() - t0) / (5 * calls)
+            kern = event_time_ms(torch, lambda: c.func_evaluatef(11, x, out=o), 50) * 1e-3
+            res[f"d{d}"] = {"eager_us": eager * 1e6, "graph_us": graph * 1e6, "kernel_us": kern * 1e6,
+                            "evals_per_s_graph": 50 / graph}
+            del g
+        finally:
+            torch.cuda.synchronize()
+            c.set_stream(None)
+            c.dispose()
+    return res
 
 
 def pmc_summary(fetch_dir: str, write_dir: str) -> None:
