@@ -355,6 +355,9 @@ __device__ __forceinline__ void resident_eval(const DevProb &pb, const typename 
     if (ROT) {
       copy_to_lds(smem + L.q, pb.qfrag, L.q_bytes);
       copy_to_lds(smem + L.goff, pb.goff, L.goff_bytes);
+      // the k ranges go to LDS too: read from global memory inside the loop, their vector-memory
+      // wait would also wait for the next row group's prefetch
+      copy_to_lds(smem + L.mtab, pb.mtab, L.mtab_bytes);
     }
     copy_to_lds(smem + L.oh, pb.oh, L.vec_bytes);
     copy_to_lds(smem + L.cz, pb.cz, L.mp_bytes);
@@ -369,7 +372,7 @@ __device__ __forceinline__ void resident_eval(const DevProb &pb, const typename 
   const T prm = kind_param<KIND, T>(pb.Df, pb.kparam);
   const unsigned char *Yb = reinterpret_cast<const unsigned char *>(Y + r * S);
   const int bstride = kRowsPerBlock * S * static_cast<int>(sizeof(T));
-  const int4 *mtab = reinterpret_cast<const int4 *>(pb.mtab);
+  const int4 *s_mtab = reinterpret_cast<const int4 *>(smem + L.mtab);
 
   for (; g < gend; g += gstride) {
     const int row0 = g * ROWS;
@@ -388,8 +391,11 @@ __device__ __forceinline__ void resident_eval(const DevProb &pb, const typename 
       if constexpr (KT_::pairwise) wave_sync();  // the rows are overwritten with z below
     }
     auto rotate_m = [&](Acc4 (&acc)[NB], int mm) {
-      if constexpr (SB) mtile_stream<P>(acc, mtab[mm], s_goff, Yb, s_q, lane, q);
-      else mtile<P>(acc, mtab[mm], bf, s_q, lane);
+      const int4 mv = s_mtab[mm];
+      const int4 mi = make_int4(__builtin_amdgcn_readfirstlane(mv.x), __builtin_amdgcn_readfirstlane(mv.y),
+                                __builtin_amdgcn_readfirstlane(mv.z), 0);
+      if constexpr (SB) mtile_stream<P>(acc, mi, s_goff, Yb, s_q, lane, q);
+      else mtile<P>(acc, mi, bf, s_q, lane);
     };
 
     Acc<T> a[NB];

@@ -11,8 +11,8 @@
 namespace curob {
 
 struct LdsLayout {
-  int q, goff, oh, cz, coef, succ, y;  // byte offsets
-  int q_bytes, goff_bytes, vec_bytes, mp_bytes, succ_bytes, slice_bytes;
+  int q, goff, oh, cz, coef, succ, mtab, y;  // byte offsets
+  int q_bytes, goff_bytes, vec_bytes, mp_bytes, succ_bytes, mtab_bytes, slice_bytes;
   int fixed;  // bytes before the per-wave slices
   int total;
 };
@@ -29,8 +29,8 @@ __host__ __device__ constexpr int max_waves_of(int path) {
 }
 
 // LDS carve of the resident kernel: rotation tiles, gather offsets, per-variable shift,
-// per-position tables, then one slice per wave holding its rows (16 per column block) plus one
-// spill row, S elements each.
+// per-position tables, the per-m-tile k ranges, then one slice per wave holding its rows (16 per
+// column block) plus one spill row, S elements each.
 __host__ __device__ inline LdsLayout lds_layout(int path, const DevProb &pb, int nwaves) {
   const int esz = path == PATH_F64 ? 8 : 4;
   const int kw = kw_of(path);
@@ -41,6 +41,7 @@ __host__ __device__ inline LdsLayout lds_layout(int path, const DevProb &pb, int
   L.vec_bytes = round16(pb.D * esz);
   L.mp_bytes = round16(16 * pb.MT * esz);
   L.succ_bytes = round16(16 * pb.MT * 2);
+  L.mtab_bytes = pb.rotated ? 16 * pb.MT : 0;
   L.slice_bytes = round16((rows + 1) * pb.S * esz);
   int off = 0;
   L.q = off;
@@ -55,6 +56,8 @@ __host__ __device__ inline LdsLayout lds_layout(int path, const DevProb &pb, int
   off += L.mp_bytes;
   L.succ = off;
   off += L.succ_bytes;
+  L.mtab = off;
+  off += L.mtab_bytes;
   L.y = off;
   L.fixed = off;
   off += L.slice_bytes * nwaves;
