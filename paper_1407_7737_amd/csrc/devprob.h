@@ -33,7 +33,9 @@ inline constexpr int blocks_of(int) { return 1; }
 
 struct DevProb {
   // every pointer is device memory owned by the library
-  const void *oh;        // shift rounded to the path's type, original variable order, D entries
+  const void *oh;        // shift rounded to the path's type: original variable order (D entries),
+                         // or on the split paths packed order (max(KT*KW, 16*MT) entries, zeros
+                         // past D)
   const uint16_t *goff;  // packed position -> byte offset of its variable in an LDS row; KT*KW
                          // entries, padding -> the zero slot at D
   const void *cz;        // per packed position (16*MT entries) offset c' added after the rotation:
@@ -41,7 +43,8 @@ struct DevProb {
   const void *coef;      // per packed position coefficient (elliptic weights, 1/sqrt(i), ...)
   const int16_t *succ;   // per packed position: packed position of the formula successor or -1
   const void *qfrag;     // nonzero tiles of s*Qp in MFMA operand order (path-specific layout)
-  const int *mtab;       // per m-tile: first k-tile, last k-tile, first tile index, 0
+  const int *mtab;       // per m-tile: first k-tile, last k-tile, first tile index and, on the
+                         // split paths, 4 * first k-tile + (last - first) (0 elsewhere)
   int D;                 // dimension
   int S;                 // LDS row stride in elements (4*odd, >= D+1 and >= 16*MT)
   int KT;                // k-tiles

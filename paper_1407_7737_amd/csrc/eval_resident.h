@@ -96,6 +96,12 @@ struct XTile {
   using L = typename std::conditional<VEC, V, T>::type;
   L v[CMAX];
 
+  // registers past the row group's loads stay zero (raw staging stores them to the spill row)
+  __device__ __forceinline__ void clear() {
+#pragma unroll
+    for (int t = 0; t < CMAX; ++t) v[t] = L{};
+  }
+
   __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t rs, int nload, int lane) {
 #pragma unroll
     for (int t = 0; t < CMAX; ++t) {
@@ -112,8 +118,11 @@ struct XTile {
     }
   }
 
-  // Y[r][j] = x[r][j] - o_hi[j] for the wave's rows; elements past the last row land in the
-  // spill row ROWS of the slice.
+  // Y[r][j] = x[r][j] - o_hi[j] (RAW: x[r][j]; the split paths subtract o_hi later, in packed
+  // order) for the wave's rows; elements past the last row land in the spill row ROWS of the
+  // slice.  RAW stores need neither a shift read nor a guard: registers past nload hold zeros
+  // and only reach the spill row.
+  template <bool RAW>
   __device__ __forceinline__ void stage(int nload, int D, int S, T *Y, const T *oh, int lane) const {
     const int e0 = lane * NV;
     int rr = e0 / D, jj = e0 - rr * D;
@@ -121,12 +130,16 @@ struct XTile {
     const int dr = step / D, dj = step - dr * D;
 #pragma unroll
     for (int t = 0; t < CMAX; ++t) {
-      if (t < nload) {
+      if (RAW || t < nload) {
         const int ra = rr < ROWS ? rr : ROWS;
-        if constexpr (VEC)
+        if constexpr (RAW) {
+          if constexpr (VEC) *reinterpret_cast<V *>(Y + ra * S + jj) = v[t];
+          else Y[ra * S + jj] = v[t];
+        } else if constexpr (VEC) {
           *reinterpret_cast<V *>(Y + ra * S + jj) = v[t] - *reinterpret_cast<const V *>(oh + jj);
-        else
+        } else {
           Y[ra * S + jj] = v[t] - oh[jj];
+        }
       }
       jj += dj;
       rr += dr;
@@ -168,12 +181,13 @@ struct RotOps<PATH_F64> {
 };
 
 // Gathers this lane's B operand of every k-tile and column block from the staged rows (packed
-// order via the byte offsets s_goff) and, on the split paths, cuts each y into bf16 terms
-// (y - hi and the next residual are exact in FP32).  Yb: row r of column block 0.
+// order via the byte offsets s_goff) and, on the split paths, subtracts o_hi (s_ohp, packed
+// order) and cuts each y into bf16 terms (y - hi and the next residual are exact in FP32).
+// Yb: row r of column block 0.
 template <int P>
 __device__ __forceinline__ void gather_b(typename RotOps<P>::Frag (&bf)[RotOps<P>::NTERM][blocks_of(P)][RotOps<P>::KTMAX],
                                          int KT, const uint16_t *s_goff, const unsigned char *Yb, int bstride,
-                                         int q) {
+                                         int q, const float *s_ohp) {
   using R = RotOps<P>;
   constexpr int NB = blocks_of(P);
 #pragma unroll
@@ -182,14 +196,19 @@ __device__ __forceinline__ void gather_b(typename RotOps<P>::Frag (&bf)[RotOps<P
       if constexpr (is_split(P)) {
         const uint4 idx = *reinterpret_cast<const uint4 *>(s_goff + kt * 32 + q * 8);
         const uint32_t iw[4] = {idx.x, idx.y, idx.z, idx.w};
+        // the rows hold x: y = x - o_hi with o_hi in packed order (one rounding, as when staged)
+        const f32x4 oa = *reinterpret_cast<const f32x4 *>(s_ohp + kt * 32 + q * 8);
+        const f32x4 ob = *reinterpret_cast<const f32x4 *>(s_ohp + kt * 32 + q * 8 + 4);
+        const float ov[8] = {oa[0], oa[1], oa[2], oa[3], ob[0], ob[1], ob[2], ob[3]};
 #pragma unroll
         for (int e = 0; e < 8; e += 2) {
           // two elements at a time: one packed conversion per term for the pair
           const uint32_t o0 = iw[e >> 1] & 0xFFFFu, o1 = iw[e >> 1] >> 16;
+          const f32x2 oo = {ov[e], ov[e + 1]};
 #pragma unroll
           for (int b = 0; b < NB; ++b) {
-            const f32x2 y = {*reinterpret_cast<const float *>(Yb + b * bstride + o0),
-                             *reinterpret_cast<const float *>(Yb + b * bstride + o1)};
+            const f32x2 y = f32x2{*reinterpret_cast<const float *>(Yb + b * bstride + o0),
+                                  *reinterpret_cast<const float *>(Yb + b * bstride + o1)} - oo;
             const bf16x2 h = __builtin_convertvector(y, bf16x2);
             const f32x2 r1 = y - __builtin_convertvector(h, f32x2);
             bf[0][b][kt][e] = h[0];
@@ -266,6 +285,62 @@ __device__ __forceinline__ void mtile(typename PathT<P>::Acc4 (&acc)[blocks_of(P
         }
       }
     }
+  }
+}
+
+// One m-tile on the split paths for a k range fixed at compile time (k-tiles KX .. KX+NK-1):
+// the range's rotation fragments are read from LDS together, ahead of the first product, so
+// one LDS latency is exposed per m-tile, and the products run with no branch between them.
+template <int P, int KX, int NK>
+__device__ __forceinline__ void mtile_fixed(typename PathT<P>::Acc4 (&acc)[blocks_of(P)], int t0,
+                                            const bf16x8 (&bf)[RotOps<P>::NTERM][blocks_of(P)][RotOps<P>::KTMAX],
+                                            const unsigned char *s_q, int lane) {
+  constexpr int NT = RotOps<P>::NTERM;
+  constexpr int NB = blocks_of(P);
+  const bf16x8 *qf = reinterpret_cast<const bf16x8 *>(s_q) + t0 * (64 * NT) + lane;
+  bf16x8 qa[NK][NT];
+#pragma unroll
+  for (int j = 0; j < NK; ++j)
+#pragma unroll
+    for (int u = 0; u < NT; ++u) qa[j][u] = qf[(j * NT + u) * 64];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) acc[b] = f32x4{0, 0, 0, 0};
+#pragma unroll
+  for (int j = 0; j < NK; ++j) {
+    const int kt = KX + j;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      if constexpr (NT == 3) {
+        // the six products of total order <= 2 in the 2^-8 splitting, smallest first
+        acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(qa[j][2], bf[0][b][kt], acc[b], 0, 0, 0);
+        acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(qa[j][1], bf[1][b][kt], acc[b], 0, 0, 0);
+        acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(qa[j][0], bf[2][b][kt], acc[b], 0, 0, 0);
+        acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(qa[j][1], bf[0][b][kt], acc[b], 0, 0, 0);
+        acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(qa[j][0], bf[1][b][kt], acc[b], 0, 0, 0);
+        acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(qa[j][0], bf[0][b][kt], acc[b], 0, 0, 0);
+      } else {
+        acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(qa[j][1], bf[0][b][kt], acc[b], 0, 0, 0);
+        acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(qa[j][0], bf[1][b][kt], acc[b], 0, 0, 0);
+        acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(qa[j][0], bf[0][b][kt], acc[b], 0, 0, 0);
+      }
+    }
+  }
+}
+
+// Calls f(std::integral_constant<int, C>) for the k-range code C = 4 * first k-tile + (k-tiles - 1)
+// of an m-tile (split paths: at most four k-tiles of 32).
+template <typename F>
+__device__ __forceinline__ void dispatch_krange(int code, F &&f) {
+  switch (code) {
+#define CUROB_KCASE(C) \
+  case C:              \
+    f(std::integral_constant<int, C>{}); \
+    break;
+    CUROB_KCASE(0) CUROB_KCASE(1) CUROB_KCASE(2) CUROB_KCASE(3) CUROB_KCASE(4) CUROB_KCASE(5)
+    CUROB_KCASE(6) CUROB_KCASE(8) CUROB_KCASE(9) CUROB_KCASE(12)
+#undef CUROB_KCASE
+    default:
+      break;
   }
 }
 
@@ -349,6 +424,7 @@ __device__ __forceinline__ void resident_eval(const DevProb &pb, const typename 
 
   // the first row group's loads go out before the tables are copied
   Tile xt;
+  if constexpr (is_split(P)) xt.clear();
   if (g < gend) xt.load(rows_rsrc(x, g * ROWS, n, D), nload, lane);
   T *Y = reinterpret_cast<T *>(smem + L.y + wave * L.slice_bytes);
   if (setup) {
@@ -377,7 +453,7 @@ __device__ __forceinline__ void resident_eval(const DevProb &pb, const typename 
   for (; g < gend; g += gstride) {
     const int row0 = g * ROWS;
     wave_sync();
-    xt.stage(nload, D, S, Y, s_oh, lane);
+    xt.template stage<is_split(P)>(nload, D, S, Y, s_oh, lane);
     // the next row group's loads are in flight during everything below
     const int gn = g + gstride;
     if (gn < gend) xt.load(rows_rsrc(x, gn * ROWS, n, D), nload, lane);
@@ -387,7 +463,7 @@ __device__ __forceinline__ void resident_eval(const DevProb &pb, const typename 
     constexpr bool SB = ROT && !is_split(P) && !KT_::pairwise && NB == 1;
     typename R::Frag bf[R::NTERM][NB][R::KTMAX];
     if constexpr (ROT && !SB) {
-      gather_b<P>(bf, pb.KT, s_goff, Yb, bstride, q);
+      gather_b<P>(bf, pb.KT, s_goff, Yb, bstride, q, reinterpret_cast<const float *>(s_oh));
       if constexpr (KT_::pairwise) wave_sync();  // the rows are overwritten with z below
     }
     auto rotate_m = [&](Acc4 (&acc)[NB], int mm) {
@@ -396,6 +472,18 @@ __device__ __forceinline__ void resident_eval(const DevProb &pb, const typename 
                                 __builtin_amdgcn_readfirstlane(mv.z), 0);
       if constexpr (SB) mtile_stream<P>(acc, mi, s_goff, Yb, s_q, lane, q);
       else mtile<P>(acc, mi, bf, s_q, lane);
+    };
+    // six-product path: the m-tile's k range selects a branch-free product sequence
+    constexpr bool FIX = ROT && P == PATH_SPLIT6;
+    auto rotate_fix = [&](Acc4 (&acc)[NB], int4 mv) {
+      if constexpr (FIX) {
+        const int code = __builtin_amdgcn_readfirstlane(mv.w);
+        const int t0 = __builtin_amdgcn_readfirstlane(mv.z);
+        dispatch_krange(code, [&](auto c) {
+          constexpr int C = decltype(c)::value;
+          mtile_fixed<P, C / 4, C % 4 + 1>(acc, t0, bf, s_q, lane);
+        });
+      }
     };
 
     Acc<T> a[NB];
@@ -407,21 +495,38 @@ __device__ __forceinline__ void resident_eval(const DevProb &pb, const typename 
     // (not on the FP64 path, whose doubled accumulators would not fit the registers)
     constexpr bool PIPE = P != PATH_F64;
     Acc4 acc_cur[NB], acc_nxt[NB];
-    if constexpr (ROT && PIPE) rotate_m(acc_cur, 0);
+    int4 mv_next = make_int4(0, 0, 0, 0);  // k range of m-tile m + 1, read one m-tile ahead
+    if constexpr (FIX) {
+      rotate_fix(acc_cur, s_mtab[0]);
+      mv_next = s_mtab[MT > 1 ? 1 : 0];
+    } else if constexpr (ROT && PIPE) {
+      rotate_m(acc_cur, 0);
+    }
     for (int m = 0; m < MT; ++m) {
       T z[NB][4];
+      // the m-tile's per-position tables are read before the next m-tile's products are
+      // issued, so their LDS latency hides behind the MFMAs
+      T c4[4], cf[4] = {T(0), T(0), T(0), T(0)};
+      if constexpr (P == PATH_F64 && ROT) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) c4[e] = s_cz[frag_pos<P, ROT>(m, q, e)];
+        if constexpr (KT_::needs_coef && !KT_::pairwise) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) cf[e] = s_coef[frag_pos<P, ROT>(m, q, e)];
+        }
+      } else {
+        read4(c4, s_cz, 16 * m + 4 * q);
+        if constexpr (KT_::needs_coef && !KT_::pairwise) read4(cf, s_coef, 16 * m + 4 * q);
+      }
       if constexpr (ROT) {
-        if constexpr (PIPE) {
+        if constexpr (FIX) {
+          const int4 mv2 = s_mtab[m + 2 < MT ? m + 2 : MT - 1];
+          if (m + 1 < MT) rotate_fix(acc_nxt, mv_next);
+          mv_next = mv2;
+        } else if constexpr (PIPE) {
           if (m + 1 < MT) rotate_m(acc_nxt, m + 1);
         } else {
           rotate_m(acc_cur, m);
-        }
-        T c4[4];
-        if constexpr (P == PATH_F64) {
-#pragma unroll
-          for (int e = 0; e < 4; ++e) c4[e] = s_cz[frag_pos<P, ROT>(m, q, e)];
-        } else {
-          read4(c4, s_cz, 16 * m + 4 * q);
         }
 #pragma unroll
         for (int b = 0; b < NB; ++b)
@@ -432,12 +537,17 @@ __device__ __forceinline__ void resident_eval(const DevProb &pb, const typename 
           for (int b = 0; b < NB; ++b) acc_cur[b] = acc_nxt[b];
         }
       } else {
-        T c4[4];
-        read4(c4, s_cz, 16 * m + 4 * q);
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
           T y4[4];
           read4(y4, Y + (b * kRowsPerBlock + r) * S, 16 * m + 4 * q);
+          if constexpr (is_split(P)) {
+            // raw rows: y = x - o_hi here (packed order is the original order when unrotated)
+            T o4[4];
+            read4(o4, s_oh, 16 * m + 4 * q);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) y4[e] -= o4[e];
+          }
 #pragma unroll
           for (int e = 0; e < 4; ++e) z[b][e] = scale * y4[e] + c4[e];
         }
@@ -449,15 +559,6 @@ __device__ __forceinline__ void resident_eval(const DevProb &pb, const typename 
 #pragma unroll
           for (int e = 0; e < 4; ++e) Y[(b * kRowsPerBlock + r) * S + frag_pos<P, ROT>(m, q, e)] = z[b][e];
       } else {
-        T cf[4] = {T(0), T(0), T(0), T(0)};
-        if constexpr (KT_::needs_coef) {
-          if constexpr (P == PATH_F64 && ROT) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) cf[e] = s_coef[frag_pos<P, ROT>(m, q, e)];
-          } else {
-            read4(cf, s_coef, 16 * m + 4 * q);
-          }
-        }
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
           T v[3] = {T(0), T(0), T(0)};

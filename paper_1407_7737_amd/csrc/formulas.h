@@ -92,8 +92,9 @@ __device__ __forceinline__ T schwefel_g1(T w, T inv10000n) {
     const float u = far ? 500.0f - m : a;
     const float d = __builtin_fmaxf(a - 500.0f, 0.0f);
     // sqrt(u) <= sqrt(500) < 23: the sine's argument in revolutions stays below 4, inside
-    // the hardware sine's domain, so no range reduction is needed
-    const float sn = __builtin_amdgcn_sinf(__builtin_sqrtf(u) * 0.15915494309189535f);
+    // the hardware sine's domain, so no range reduction is needed.  The hardware square root
+    // (1 ulp) moves the phase by at most 23 x 2^-23 rad, the order of the revolution rounding.
+    const float sn = __builtin_amdgcn_sinf(__builtin_amdgcn_sqrtf(u) * 0.15915494309189535f);
     return __builtin_copysignf(u, w) * sn - d * d * inv10000n;
   } else {
     T m = a - T(500) * t_floor(a * T(0.002));  // mod(a, 500); the floor may be off by one

@@ -38,7 +38,10 @@ __host__ __device__ inline LdsLayout lds_layout(int path, const DevProb &pb, int
   LdsLayout L;
   L.q_bytes = pb.rotated ? round16(pb.ntiles * 64 * (is_split(path) ? 16 * split_terms(path) : esz)) : 0;
   L.goff_bytes = pb.rotated ? round16(pb.KT * kw * 2) : 0;
-  L.vec_bytes = round16(pb.D * esz);
+  // o_hi: original order (D entries), or packed order on the split paths (KT * KW and 16 * MT
+  // positions, zeros past D)
+  const int nvec = is_split(path) ? (pb.KT * kw > 16 * pb.MT ? pb.KT * kw : 16 * pb.MT) : pb.D;
+  L.vec_bytes = round16((nvec > pb.D ? nvec : pb.D) * esz);
   L.mp_bytes = round16(16 * pb.MT * esz);
   L.succ_bytes = round16(16 * pb.MT * 2);
   L.mtab_bytes = pb.rotated ? 16 * pb.MT : 0;

@@ -85,13 +85,16 @@ bool build_host_tables(const Problem &p, int path, HostTables &ht, std::string &
     order[pp] = rotate ? p.orig[pp] : pp;
     slot[order[pp]] = pp;
   }
-  // shift: the path's rounding o_hi, and (FP32 paths) the remainder o_lo = o - o_hi
+  // shift: the path's rounding o_hi, and (FP32 paths) the remainder o_lo = o - o_hi.  The
+  // split paths subtract o_hi while gathering the packed operand, so they keep it in packed
+  // order (zeros past D); the other paths subtract it in original order while staging rows.
   std::vector<double> olo(D, 0.0);
-  ht.oh.assign(pad16(D * esz), 0);
+  const bool split = is_split(path);
+  ht.oh.assign(pad16(static_cast<size_t>(split ? std::max(D, std::max(KT * KW, Mp)) : D) * esz), 0);
   for (int j = 0; j < D; ++j) {
-    store(ht.oh, j, p.o[j]);
     if (!f64) olo[j] = p.o[j] - static_cast<double>(static_cast<float>(p.o[j]));
   }
+  for (int pp = 0; pp < D; ++pp) store(ht.oh, pp, p.o[split ? order[pp] : pp]);
   // packed block-diagonal rotation, scaled by s
   const int nb = static_cast<int>(p.Q.size());
   auto qp = [&](int row, int col) -> double {
@@ -157,6 +160,8 @@ bool build_host_tables(const Problem &p, int path, HostTables &ht, std::string &
       ht.mtab[4 * m + 0] = klo;
       ht.mtab[4 * m + 1] = khi;
       ht.mtab[4 * m + 2] = static_cast<int>(tiles.size());
+      // split paths (k-tiles of 32, at most four): the range as one dispatch code
+      if (is_split(path)) ht.mtab[4 * m + 3] = 4 * klo + (khi - klo);
       for (int kt = klo; kt <= khi; ++kt) tiles.emplace_back(m, kt);
     }
     ntiles = static_cast<int>(tiles.size());
