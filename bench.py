@@ -42,7 +42,7 @@ NAMES = {0: "sphere", 2: "elliptic", 9: "griewank", 10: "rastrigin_u", 11: "rast
          16: "schwefel", 19: "ackley"}
 # resident kernel instance (path, formula family, rotated) each formula runs at D = 100 in the
 # default split mode: path 0 = three BF16 products, 3 = six; the sphere skips its rotation
-RESIDENT_KERNEL = {0: (0, 0, 0), 2: (3, 0, 1), 9: (0, 5, 1), 10: (0, 6, 0), 11: (0, 6, 1), 14: (0, 9, 1),
+RESIDENT_KERNEL = {0: (0, 0, 0), 2: (0, 0, 1), 9: (0, 5, 1), 10: (0, 6, 0), 11: (0, 6, 1), 14: (0, 9, 1),
                    16: (3, 10, 1), 19: (0, 13, 1)}
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_d100_n262144.json")

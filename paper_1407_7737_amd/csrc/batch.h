@@ -26,7 +26,9 @@ constexpr int kBatchRows = kRowsPerBlock * blocks_of(PATH_SPLIT);  // rows per r
 // The variants (formula family, rotation, six products) the batch kernel runs: one per
 // Tab. 1 function fid (its family and transform, the sphere evaluated without its rotation as
 // it is rotation invariant, six products where the default split mode uses them), plus
-// Rosenbrock below dimension 10, which the default mode gives six products.
+// Rosenbrock below dimension 10, which the default mode gives six products.  The elliptic
+// function from dimension 50 on takes three products: the variant of id 1 (same family and
+// transform kind, three products).
 struct BatchVariant {
   int kind, rot, six;
 };
@@ -40,7 +42,11 @@ __host__ __device__ constexpr BatchVariant batch_variant(int v) {
       {K_HAPPYCAT, 1, 0},    {K_HGBAT, 1, 0},    {K_F6, 1, 0},      {K_ROSENBROCK, 1, 1}};
   return t[v];
 }
-inline int batch_variant_of(int fid, int dim) { return fid == 14 && dim < 10 ? 23 : fid; }
+inline int batch_variant_of(int fid, int dim) {
+  if (fid == 14 && dim < 10) return 23;
+  if (fid == 2 && dim >= 50) return 1;
+  return fid;
+}
 
 // Launches the persistent batch kernel: probs/variants/xs/outs/counts per population, items
 // (population, first row group, end row group, 0) and per-workgroup item ranges

@@ -112,11 +112,11 @@ def all_modes(c):
     return [c.MODE_SPLIT, c.MODE_FP32, c.MODE_SPLIT_BF16X3, c.MODE_SPLIT_BF16X6]
 
 
-SIX_PRODUCTS = {2, 3, 7, 8, 12, 13, 16, 17}
+SIX_PRODUCTS = {3, 7, 8, 12, 13, 16, 17}
 
 
 def six(fid, dim):
-    return fid in SIX_PRODUCTS or (fid == 14 and dim < 10)
+    return fid in SIX_PRODUCTS or (fid == 14 and dim < 10) or (fid == 2 and dim < 50)
 
 
 @pytest.mark.parametrize("dim", [129, 200, 1000])
