@@ -296,6 +296,69 @@ def pmc_summary(fetch_dir: str, write_dir: str) -> None:
     print("\n".join(lines))
 
 
+FAMILY = {0: "wsphere", 5: "griewank", 6: "rastrigin", 9: "rosenbrock", 10: "schwefel", 13: "ackley"}
+PATH_NAME = {0: "x3 split", 1: "FP32", 2: "FP64", 3: "x6 split"}
+
+
+def trace_summary(kind: str, headline_dir: str, secondary_dir: str) -> None:
+    """Per-kernel launch durations from the run_kernel_stats.csv of two rocprofv3 --kernel-trace
+    --stats runs of this script (the headline step, then the run with the secondary workloads);
+    writes profiles/resident_d100_n262144_kernel_trace.txt and profiles/secondary_kernel_trace.txt."""
+    def stats(d):
+        f = os.path.join(d, "run_kernel_stats.csv")
+        return list(csv.DictReader(open(f)))
+
+    def short(name):
+        m = re.search(r"(k_\w+)<([^>]*)>", name)
+        if m:
+            return m.group(1) + "<" + m.group(2).replace(" ", "") + ">"
+        m = re.search(r"(k_\w+)", name)
+        return m.group(1) if m else None
+
+    cmd_head = ("rocprofv3 --kernel-trace --stats --output-format csv -d <OUT> -o run -- python -u bench.py "
+                "--steps 5 --warmup 1 --no-cpu-baseline --no-secondary")
+    cmd_sec = ("rocprofv3 --kernel-trace --stats --output-format csv -d <OUT2> -o run -- python -u bench.py "
+               "--steps 2 --warmup 1 --no-cpu-baseline")
+    summ = "python bench.py --trace-summary <OUT> <OUT2>"
+    lines = ["Kernel durations, D=100, N=2^18 (bench step: 8 formulas, split path then FP64 path)", "",
+             "commands (repository root):", "  " + cmd_head, "  " + summ,
+             "source: <OUT>/run_kernel_stats.csv (11 launches per kernel: 1 warmup, 5 timed steps back to",
+             "back, then 5 steps with each launch between two HIP events for the per-launch durations).",
+             "k_eval_resident<path, family, rotated, vec>: path 0 = split BF16x3, 3 = split BF16x6, 2 = FP64;",
+             "families 0 weighted sphere, 5 Griewank, 6 Rastrigin, 9 Rosenbrock, 10 Schwefel, 13 Ackley.", "",
+             f"{'kernel':28s} {'path':9s} {'family':11s} {'rot':>3s} {'calls':>5s} {'avg us':>8s} {'min us':>8s} {'max us':>8s}"]
+    rows = []
+    for r in stats(headline_dir):
+        k = short(r["Name"])
+        if not k or not k.startswith("k_eval_resident<"):
+            continue
+        pth, fam, rot, _ = (int(v) for v in k[len("k_eval_resident<"):-1].split(","))
+        rows.append((float(r["AverageNs"]), k, pth, fam, rot, int(r["Calls"]), float(r["MinNs"]), float(r["MaxNs"])))
+    for avg, k, pth, fam, rot, calls, mn, mx in sorted(rows, reverse=True):
+        lines.append(f"{k:28s} {PATH_NAME[pth]:9s} {FAMILY.get(fam, str(fam)):11s} {rot:3d} {calls:5d} "
+                     f"{avg / 1e3:8.2f} {mn / 1e3:8.2f} {mx / 1e3:8.2f}")
+    with open(os.path.join(ROOT, "profiles", "resident_d100_n262144_kernel_trace.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+    lines = ["Kernel durations of the secondary workloads (bench.py --steps 2): D=1000 N=2^18 eight formulas",
+             "(four 65536-row passes each), hybrid and composition at D=1000 N=16384, the 64-population batch",
+             "(tuning included), 50-row latency calls; the D=100 resident kernels of the headline step as well.", "",
+             "commands (repository root):", "  " + cmd_sec, "  " + summ,
+             "source: <OUT2>/run_kernel_stats.csv; every launch of the run is counted (calls include warmups and tuning).",
+             "", f"{'kernel':60s} {'calls':>7s} {'avg us':>9s} {'total ms':>9s}"]
+    agg = {}
+    for r in stats(secondary_dir):
+        k = short(r["Name"]) or r["Name"][:60]
+        a = agg.setdefault(k, [0, 0.0])
+        a[0] += int(r["Calls"])
+        a[1] += float(r["TotalDurationNs"])
+    for k, (calls, tot) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
+        lines.append(f"{k[:60]:60s} {calls:7d} {tot / calls / 1e3:9.2f} {tot / 1e6:9.3f}")
+    with open(os.path.join(ROOT, "profiles", "secondary_kernel_trace.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines[:12]))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -305,9 +368,13 @@ def main():
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--trace-summary", nargs=2, metavar=("HEADLINE_DIR", "SECONDARY_DIR"))
     args = ap.parse_args()
     if args.pmc_summary:
         pmc_summary(*args.pmc_summary)
+        return
+    if args.trace_summary:
+        trace_summary("all", *args.trace_summary)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only: the population shards by rows "
@@ -344,14 +411,21 @@ def main():
         for _ in range(args.warmup):
             step(fp64)
         torch.cuda.synchronize()
+        # the timed steps: the eight launches back to back, nothing else on the stream
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step(fp64)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        # per-launch durations: the same steps again, each launch between two HIP events on the
+        # stream it runs on (an event pair serialises the launches around it, so these are the
+        # isolated kernel times a kernel trace reports, slightly above their share of the step)
         ev = {fid: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                     for _ in range(args.steps)] for fid in FIDS}
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
         for k in range(args.steps):
             step(fp64, {fid: ev[fid][k] for fid in FIDS})
         torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
         per = {fid: float(np.mean([a.elapsed_time(b) for a, b in ev[fid]])) for fid in FIDS}
         return wall, per
 
