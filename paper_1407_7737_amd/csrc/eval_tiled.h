@@ -10,8 +10,9 @@
 //   (one barrier per step); rotation tiles come from L2.  The epilogue applies the formula and
 //   leaves compensated per-row partial sums of the group in scratch (pairwise families store
 //   z instead).
-// k_tiled_finalize: one wave per row combines the partials of each formula segment (and, for
-//   pairwise segments, sums the neighbour terms from z), finalises and adds f_opt.
+// k_tiled_finalize: one thread per row combines the partials of each formula segment,
+//   finalises and adds f_opt; k_tiled_finalize_pairs does the same with one wave per row for
+//   problems with pairwise segments, whose neighbour terms are summed from z.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -608,6 +609,42 @@ __global__ __launch_bounds__(256) void k_tiled_finalize(TiledProb tp, const type
                                                         const typename Types<P>::T *__restrict__ zbuf, int n,
                                                         typename Types<P>::T *__restrict__ out) {
   using T = typename Types<P>::T;
+  (void)zbuf;
+  // one thread per row (problems without pair terms): the partial slots of consecutive rows
+  // are adjacent, so each output group's slots are read as one contiguous run per wave
+  const int row = blockIdx.x * 256 + threadIdx.x;
+  const bool live = row < n;
+  T F = T(0);
+  for (int si = 0; si < tp.nsegs; ++si) {
+    const TiledSeg &sg = tp.segs[si];
+    Acc<T> a;
+    a.init();
+    if (live) {
+      for (int g = sg.g0; g < sg.g1; ++g) {
+        const T *src = partials + (static_cast<size_t>(g) * kChunkRows + row) * kPartialSlots;
+        T v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = src[k];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) acc_merge(a, k, v[2 * k], v[2 * k + 1]);
+        a.p *= v[6];
+      }
+    }
+    T sm[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) sm[k] = a.get(k) - T(sg.padc[k]);
+    F += finalize_any<T>(sg.kind, sm, a.p, sg.n);
+  }
+  if (live) out[row] = F + T(tp.bias);
+}
+
+// Problems with pair terms: one wave per row, lanes over the output groups and the pair
+// positions of the row.
+template <int P>
+__global__ __launch_bounds__(256) void k_tiled_finalize_pairs(TiledProb tp, const typename Types<P>::T *__restrict__ partials,
+                                                        const typename Types<P>::T *__restrict__ zbuf, int n,
+                                                        typename Types<P>::T *__restrict__ out) {
+  using T = typename Types<P>::T;
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (row >= n) return;
@@ -741,8 +778,11 @@ hipError_t launch_tiled_path(int kind_hint, const TiledProb &tp, const void *x, 
   e = hipLaunchKernel(fn, dim3(tp.ngroups * rounds * kNumXcd), dim3(kGemmThreads), gargs, 0, st);
   if (e != hipSuccess) return e;
   void *fargs[] = {&arg, &pa, &za, &na, &oa};
-  return hipLaunchKernel(reinterpret_cast<const void *>(&k_tiled_finalize<P>), dim3((n + 3) / 4), dim3(256), fargs, 0,
-                         st);
+  if (tp.any_pairwise)
+    return hipLaunchKernel(reinterpret_cast<const void *>(&k_tiled_finalize_pairs<P>), dim3((n + 3) / 4), dim3(256),
+                           fargs, 0, st);
+  return hipLaunchKernel(reinterpret_cast<const void *>(&k_tiled_finalize<P>), dim3((n + 255) / 256), dim3(256), fargs,
+                         0, st);
 }
 
 }  // namespace tiled
