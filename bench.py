@@ -359,6 +359,54 @@ def trace_summary(kind: str, headline_dir: str, secondary_dir: str) -> None:
     print("\n".join(lines[:12]))
 
 
+def sq_summary(p1_dir: str, p2_dir: str) -> None:
+    """Per-kernel SQ instruction and busy counters of the D=100 resident kernels from two
+    rocprofv3 --pmc runs of the headline step; writes profiles/counters_d100_n262144.txt."""
+    vals = {}
+    for d in (p1_dir, p2_dir):
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for row in csv.DictReader(open(f)):
+                m = (re.search(r"k_eval_resident<(\d+), (\d+), (\d+), (\d+)>", row["Kernel_Name"])
+                     or re.search(r"k_eval_residentILi(\d+)ELi(\d+)ELi(\d+)ELi(\d+)E", row["Kernel_Name"]))
+                if not m:
+                    continue
+                key = "k_eval_resident<{},{},{},{}>".format(*m.groups())
+                vals.setdefault(key, {}).setdefault(row["Counter_Name"], []).append(float(row["Counter_Value"]))
+    simds, xcds = 1024, 8
+    groups = N // 16  # 16-row groups per launch
+    lines = ["SQ counters of the D=100 resident kernels, N=2^18 (rocprofv3 --pmc, two runs of the headline step)", "",
+             "commands (repository root):",
+             "  rocprofv3 --pmc SQ_WAVES SQ_BUSY_CYCLES SQ_WAVE_CYCLES SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_INSTS_LDS "
+             "SQ_INSTS_SALU SQ_LDS_BANK_CONFLICT GRBM_GUI_ACTIVE --output-format csv -d <P1> -- python -u bench.py "
+             "--steps 2 --warmup 1 --no-cpu-baseline --no-secondary",
+             "  rocprofv3 --pmc SQ_INSTS_MFMA SQ_VALU_MFMA_BUSY_CYCLES SQ_WAIT_ANY SQ_ACTIVE_INST_ANY SQ_INSTS_VMEM_RD "
+             "SQ_WAIT_INST_LDS SQ_INSTS_VALU_TRANS_F32 GRBM_GUI_ACTIVE --output-format csv -d <P2> -- python -u bench.py "
+             "--steps 2 --warmup 1 --no-cpu-baseline --no-secondary",
+             "  python bench.py --sq-summary <P1> <P2>", "",
+             "Per 16-row group (one wave iteration): wave-level instruction counts.  cycles: GRBM_GUI_ACTIVE / 8",
+             "XCDs (the launch under the profiler).  MFMA%: SQ_VALU_MFMA_BUSY_CYCLES / (1024 SIMDs x cycles).",
+             "VALU%: issue time of the VALU instructions at 2 cycles each plus 14 more per transcendental, per",
+             "SIMD, over cycles (a floor: dependent issue is slower).  LDS conflict: SQ_LDS_BANK_CONFLICT / 256 CUs",
+             "over cycles.  wait%: SQ_WAIT_ANY / SQ_WAVE_CYCLES (both quad-cycles).", "",
+             f"{'kernel':28s} {'VALU':>6s} {'trans':>6s} {'SALU':>6s} {'LDS':>5s} {'MFMA':>5s} {'cycles':>8s} "
+             f"{'MFMA%':>6s} {'VALU%':>6s} {'LDScf%':>6s} {'wait%':>6s}"]
+    for key in sorted(vals):
+        v = {c: float(np.median(x[1:] if len(x) > 1 else x)) for c, x in vals[key].items()}
+        cyc = v.get("GRBM_GUI_ACTIVE", 0.0) / xcds
+        if cyc <= 0:
+            continue
+        per = lambda c: v.get(c, 0.0) / groups
+        valu_cyc = (2.0 * v.get("SQ_INSTS_VALU", 0.0) + 14.0 * v.get("SQ_INSTS_VALU_TRANS_F32", 0.0)) / simds
+        lines.append(f"{key:28s} {per('SQ_INSTS_VALU'):6.0f} {per('SQ_INSTS_VALU_TRANS_F32'):6.1f} "
+                     f"{per('SQ_INSTS_SALU'):6.0f} {per('SQ_INSTS_LDS'):5.0f} {per('SQ_INSTS_MFMA'):5.0f} {cyc:8.0f} "
+                     f"{100 * v.get('SQ_VALU_MFMA_BUSY_CYCLES', 0.0) / (simds * cyc):6.1f} {100 * valu_cyc / cyc:6.1f} "
+                     f"{100 * v.get('SQ_LDS_BANK_CONFLICT', 0.0) / 256 / cyc:6.1f} "
+                     f"{100 * v.get('SQ_WAIT_ANY', 0.0) / max(v.get('SQ_WAVE_CYCLES', 1.0), 1.0):6.1f}")
+    with open(os.path.join(ROOT, "profiles", "counters_d100_n262144.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -369,12 +417,16 @@ def main():
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--trace-summary", nargs=2, metavar=("HEADLINE_DIR", "SECONDARY_DIR"))
+    ap.add_argument("--sq-summary", nargs=2, metavar=("P1_DIR", "P2_DIR"))
     args = ap.parse_args()
     if args.pmc_summary:
         pmc_summary(*args.pmc_summary)
         return
     if args.trace_summary:
         trace_summary("all", *args.trace_summary)
+        return
+    if args.sq_summary:
+        sq_summary(*args.sq_summary)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only: the population shards by rows "

@@ -49,6 +49,72 @@ void put(std::vector<unsigned char> &buf, size_t i, T v) {
 
 size_t pad16(size_t b) { return (b + 15) & ~static_cast<size_t>(15); }
 
+// Order of the variables within each rotation block (any order works: the block is permuted
+// on both sides) chosen for the LDS banks.  Each gather instruction of the split paths reads,
+// for 16 rows whose LDS stride is 4 (mod 8) words, the packed positions 32 kt + 8 q + e of
+// the four lane groups q; the 64 reads fall in distinct banks (or in pairs, with 32 banks)
+// exactly when the four variables differ mod 4.  Pairwise families also read the z of the
+// successors of positions 16 m + 4 q + e, under the same condition on the successors' packed
+// positions.  A deterministic local search over swaps within a block minimises the number of
+// repeated residues.  loc maps packed position -> index into the problem's packed order.
+void balance_banks(const Problem &p, int D, int KT, int MT, bool pair, bool wraps, std::vector<int> &loc) {
+  const int nb = static_cast<int>(p.blk_off.size());
+  std::vector<int> order(D), slot(D);
+  auto cost = [&]() {
+    for (int pp = 0; pp < D; ++pp) {
+      order[pp] = p.orig[loc[pp]];
+      slot[order[pp]] = pp;
+    }
+    int c = 0;
+    for (int kt = 0; kt < KT; ++kt)
+      for (int e = 0; e < 8; ++e) {
+        unsigned mask = 0;
+        for (int q = 0; q < 4; ++q) {
+          const int pp = 32 * kt + 8 * q + e;
+          mask |= 1u << ((pp < D ? order[pp] : D) & 3);
+        }
+        c += 4 - __builtin_popcount(mask);
+      }
+    if (pair) {
+      for (int m = 0; m < MT; ++m)
+        for (int e = 0; e < 4; ++e) {
+          unsigned mask = 0;
+          for (int q = 0; q < 4; ++q) {
+            const int pp = 16 * m + 4 * q + e;
+            int sp = pp;
+            if (pp < D) {
+              const int ni = order[pp] + 1 < D ? order[pp] + 1 : (wraps ? 0 : -1);
+              if (ni >= 0) sp = slot[ni];
+            }
+            mask |= 1u << (sp & 3);
+          }
+          c += 4 - __builtin_popcount(mask);
+        }
+    }
+    return c;
+  };
+  int best = cost();
+  uint64_t st = 0x9E3779B97F4A7C15ULL ^ static_cast<uint64_t>(D);
+  auto next = [&]() {
+    st ^= st << 13;
+    st ^= st >> 7;
+    st ^= st << 17;
+    return st;
+  };
+  for (int it = 0; it < 3000 && best > 0; ++it) {
+    const int k = static_cast<int>(next() % static_cast<uint64_t>(nb));
+    const int n = p.blk_n[k];
+    if (n < 2) continue;
+    const int a = p.blk_off[k] + static_cast<int>(next() % static_cast<uint64_t>(n));
+    const int b = p.blk_off[k] + static_cast<int>(next() % static_cast<uint64_t>(n));
+    if (a == b) continue;
+    std::swap(loc[a], loc[b]);
+    const int c = cost();
+    if (c <= best) best = c;
+    else std::swap(loc[a], loc[b]);
+  }
+}
+
 }  // namespace
 
 bool build_host_tables(const Problem &p, int path, HostTables &ht, std::string &err) {
@@ -80,9 +146,15 @@ bool build_host_tables(const Problem &p, int path, HostTables &ht, std::string &
   // The sphere is rotation invariant (Sec. 3.1): |R y|^2 = |y|^2, so it is evaluated without
   // the rotation, in original variable order.
   const bool rotate = p.rotated && !(base == 0 && c == 0.0);
+  const bool pair = kind_is_pairwise(kind), wraps = kind_pair_wraps(kind);
+  // packed position -> index into the problem's packed order: the identity, or on the rotated
+  // split paths a permutation within each block chosen for the LDS banks
+  std::vector<int> loc(D);
+  for (int pp = 0; pp < D; ++pp) loc[pp] = pp;
+  if (rotate && is_split(path)) balance_banks(p, D, KT, MT, pair, wraps, loc);
   std::vector<int> order(D), slot(D);
   for (int pp = 0; pp < D; ++pp) {
-    order[pp] = rotate ? p.orig[pp] : pp;
+    order[pp] = rotate ? p.orig[loc[pp]] : pp;
     slot[order[pp]] = pp;
   }
   // shift: the path's rounding o_hi, and (FP32 paths) the remainder o_lo = o - o_hi.  The
@@ -99,6 +171,8 @@ bool build_host_tables(const Problem &p, int path, HostTables &ht, std::string &
   const int nb = static_cast<int>(p.Q.size());
   auto qp = [&](int row, int col) -> double {
     if (!rotate || row >= D || col >= D) return 0.0;
+    row = loc[row];
+    col = loc[col];
     for (int k = 0; k < nb; ++k) {
       const int off = p.blk_off[k], n = p.blk_n[k];
       if (row >= off && row < off + n) {
@@ -118,7 +192,6 @@ bool build_host_tables(const Problem &p, int path, HostTables &ht, std::string &
   ht.cz.assign(pad16(Mp * esz), 0);
   ht.coef.assign(pad16(Mp * esz), 0);
   ht.succ.assign(pad16(Mp * 2) / 2, static_cast<int16_t>(-1));
-  const bool pair = kind_is_pairwise(kind), wraps = kind_pair_wraps(kind);
   for (int pp = 0; pp < Mp; ++pp) {
     if (pp >= D) {
       if (kind == K_POWERS) store(ht.coef, pp, 2.0);
