@@ -390,10 +390,18 @@ __device__ __forceinline__ void mtile_epilogue(const TiledProb &tp, const TiledS
     for (int cb = 0; cb < kWaveR; ++cb) {
       const int row = row0 + 16 * (kWaveR * rq + cb) + r;
       if (row < n) {
+        if constexpr (P == PATH_F64) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int pp = pm + frag_pos<P>(q, e);
-          zbuf[static_cast<size_t>(row) * tp.Dp + pp] = T(acc[cb][e]) + cz[pp];
+          for (int e = 0; e < 4; ++e) {
+            const int pp = pm + frag_pos<P>(q, e);
+            zbuf[static_cast<size_t>(row) * tp.Dp + pp] = T(acc[cb][e]) + cz[pp];
+          }
+        } else {
+          // positions pm + 4 q .. + 3 are consecutive and 16-byte aligned: one vector store
+          const int pp = pm + 4 * q;
+          const f32x4 c4 = *reinterpret_cast<const f32x4 *>(cz + pp);
+          *reinterpret_cast<f32x4 *>(zbuf + static_cast<size_t>(row) * tp.Dp + pp) =
+              f32x4{float(acc[cb][0]), float(acc[cb][1]), float(acc[cb][2]), float(acc[cb][3])} + c4;
         }
       }
     }
