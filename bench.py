@@ -77,7 +77,7 @@ def measured_traffic(fid: int):
     return None if k is None else k.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(x32: np.ndarray, budget_s: float = 12.0):
+def cpu_baseline(x32: np.ndarray, gpu: dict, budget_s: float = 12.0):
     """The oracle as it stands, on the host cores, on a bounded sample of the same rows: chunks
     of the population (wrapping around) on all measured formulas until about budget_s seconds
     of CPU work have been timed."""
@@ -86,13 +86,24 @@ def cpu_baseline(x32: np.ndarray, budget_s: float = 12.0):
     probs = {fid: oracle.basic(fid, DIM, 0) for fid in FIDS}
     chunk = 4096
     total_rows, t_total, start = 0, 0.0, 0
+    errors = {}
     while t_total < budget_s:
         idx = (start + np.arange(chunk)) % N
         sample = x32[idx].astype(np.float64)
         t0 = time.perf_counter()
-        for fid in FIDS:
-            probs[fid](sample, threads=threads)
+        ref = {fid: probs[fid](sample, threads=threads) for fid in FIDS}
         t_total += time.perf_counter() - t0
+        if not errors:
+            # the first chunk also checks the timed GPU outputs of the same rows (FP32 inputs
+            # widened exactly, so both paths see the oracle's points): |f - f_oracle| / max(1, |f_oracle|)
+            for fid in FIDS:
+                split, fp64 = gpu[fid]
+                scale = np.maximum(1.0, np.abs(ref[fid]))
+                es = np.abs(split[idx].astype(np.float64) - ref[fid]) / scale
+                e64 = np.abs(fp64[idx] - ref[fid]) / scale
+                errors[NAMES[fid]] = {"split_max_rel_err": float(es.max()), "split_rows_over_1e-4": int((es > 1e-4).sum()),
+                                      "fp64_max_rel_err": float(e64.max()), "fp64_rows_over_1e-10": int((e64 > 1e-10).sum()),
+                                      "rows": int(idx.size)}
         total_rows += chunk * len(FIDS)
         start = (start + chunk) % N
         chunk = min(chunk * 2, 1 << 16)
@@ -104,6 +115,7 @@ def cpu_baseline(x32: np.ndarray, budget_s: float = 12.0):
         "sample": f"{total_rows // len(FIDS)} rows of the D={DIM} population (consecutive chunks, wrapping) on "
                   f"each of the {len(FIDS)} formulas, {total_rows} evaluations in {t_total:.1f} s; FP64 "
                   f"dense-rotation oracle, OpenMP over rows",
+        "errors_vs_oracle": errors,
     }
 
 
@@ -535,7 +547,8 @@ def main():
     if not args.no_secondary:
         res["secondary"] = secondary(torch, c)
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(x32h)
+        gpu = {fid: (outs32[fid].cpu().numpy(), outs64[fid].cpu().numpy()) for fid in FIDS}
+        res["cpu_baseline"] = cpu_baseline(x32h, gpu)
     print(json.dumps(res), flush=True)
 
 
