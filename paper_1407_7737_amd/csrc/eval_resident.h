@@ -1,16 +1,15 @@
 // eval_resident.h -- fused evaluation kernel for basic functions of dimension <= 128.
 //
-// Each wave evaluates 16 * NB candidate rows per iteration (NB column blocks of 16) and loops
-// over row groups (grid-stride):
+// Each wave evaluates 16 candidate rows per iteration and loops over row groups (grid-stride):
 //   1. stage   the rows' x (contiguous in HBM) arrived in registers during the previous
-//              iteration through bounds-checked buffer loads; y = x - o_hi goes to the wave's
-//              LDS slice, and the loads of the next row group are issued at once so that HBM
-//              traffic overlaps everything below;
+//              iteration through bounds-checked buffer loads; they go to the wave's LDS slice
+//              (the FP32/FP64-MFMA paths store y = x - o_hi, the split paths store x and
+//              subtract o_hi in the gather), and the loads of the next row group are issued at
+//              once so that HBM traffic overlaps everything below;
 //   2. rotate  Z^T = (s Qp) Y^T on the matrix cores over the nonzero tiles of the packed
 //              block-diagonal rotation (Sec. 1.2: three random variable groups, one orthonormal
 //              block each).  The B operand is gathered from LDS in group order; on the split
-//              paths each y is cut into bf16 terms and the products accumulate in FP32.  Every
-//              rotation tile read from LDS feeds all NB column blocks;
+//              paths each y is cut into bf16 terms and the products accumulate in FP32;
 //   3. phi     z = acc + c' and the formula, straight from the accumulator fragment (pairwise
 //              families first exchange z through LDS to reach z_{i+1}); padded positions are
 //              laid out so that they add exactly known constants, removed at the end;
@@ -237,8 +236,9 @@ __device__ __forceinline__ void gather_b(typename RotOps<P>::Frag (&bf)[RotOps<P
   }
 }
 
-// One m-tile of Z^T = (s Qp) Y^T for all column blocks: acc[b] element e is packed position
-// frag_pos(m, q, e).  mi = (first k-tile, last k-tile, first tile index) of m-tile m.
+// One m-tile of Z^T = (s Qp) Y^T for all column blocks on the FP32 and FP64 MFMA paths (the
+// split paths use mtile_fixed): acc[b] element e is packed position frag_pos(m, q, e).
+// mi = (first k-tile, last k-tile, first tile index) of m-tile m.
 template <int P>
 __device__ __forceinline__ void mtile(typename PathT<P>::Acc4 (&acc)[blocks_of(P)], int4 mi,
                                       const typename RotOps<P>::Frag (&bf)[RotOps<P>::NTERM][blocks_of(P)][RotOps<P>::KTMAX],
@@ -252,29 +252,7 @@ __device__ __forceinline__ void mtile(typename PathT<P>::Acc4 (&acc)[blocks_of(P
   for (int kt = 0; kt < R::KTMAX; ++kt) {
     if (kt >= mi.x && kt <= mi.y) {
       const int t = mi.z + kt - mi.x;
-      if constexpr (P == PATH_SPLIT6) {
-        // the six products of total order <= 2 in the 2^-8 splitting, smallest first
-        const bf16x8 *qf = reinterpret_cast<const bf16x8 *>(s_q) + t * 192 + lane;
-        const bf16x8 ah = qf[0], am = qf[64], al = qf[128];
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-          acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bf[0][b][kt], acc[b], 0, 0, 0);
-          acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bf[1][b][kt], acc[b], 0, 0, 0);
-          acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bf[2][b][kt], acc[b], 0, 0, 0);
-          acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bf[0][b][kt], acc[b], 0, 0, 0);
-          acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bf[1][b][kt], acc[b], 0, 0, 0);
-          acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bf[0][b][kt], acc[b], 0, 0, 0);
-        }
-      } else if constexpr (P == PATH_SPLIT) {
-        const bf16x8 *qf = reinterpret_cast<const bf16x8 *>(s_q) + t * 128 + lane;
-        const bf16x8 ah = qf[0], al = qf[64];
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-          acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bf[0][b][kt], acc[b], 0, 0, 0);
-          acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bf[1][b][kt], acc[b], 0, 0, 0);
-          acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bf[0][b][kt], acc[b], 0, 0, 0);
-        }
-      } else {
+      {
         const auto a = reinterpret_cast<const typename R::Frag *>(s_q)[t * 64 + lane];
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
@@ -471,10 +449,10 @@ __device__ __forceinline__ void resident_eval(const DevProb &pb, const typename 
       const int4 mi = make_int4(__builtin_amdgcn_readfirstlane(mv.x), __builtin_amdgcn_readfirstlane(mv.y),
                                 __builtin_amdgcn_readfirstlane(mv.z), 0);
       if constexpr (SB) mtile_stream<P>(acc, mi, s_goff, Yb, s_q, lane, q);
-      else mtile<P>(acc, mi, bf, s_q, lane);
+      else if constexpr (!is_split(P)) mtile<P>(acc, mi, bf, s_q, lane);
     };
-    // six-product path: the m-tile's k range selects a branch-free product sequence
-    constexpr bool FIX = ROT && P == PATH_SPLIT6;
+    // split paths: the m-tile's k range selects a branch-free product sequence
+    constexpr bool FIX = ROT && is_split(P);
     auto rotate_fix = [&](Acc4 (&acc)[NB], int4 mv) {
       if constexpr (FIX) {
         const int code = __builtin_amdgcn_readfirstlane(mv.w);

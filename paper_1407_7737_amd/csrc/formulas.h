@@ -172,7 +172,10 @@ __device__ __forceinline__ void phi(T (&v)[3], T &p, T z, T zn, T coef, T prm) {
     const T e = z - T(1);
     const T g2 = T(100) * d * d + e * e;
     T cg;
-    if constexpr (sizeof(T) == 4) cg = cosf(g2); else cg = cos(g2);
+    // FP32: g2 / (2 pi) in revolutions, reduced exactly, then the hardware cosine.  The phase
+    // error is the rounding of g2 / (2 pi), 2^-24 g2, while f grows as g2^2 / 4000: the cosine
+    // error stays far below the FP32 bar for every g2
+    if constexpr (sizeof(T) == 4) cg = cos_2pi(g2 * 0.15915494309189535f); else cg = cos(g2);
     v[0] += g2 * g2 * T(1.0 / 4000.0) - cg + T(1);
   } else if constexpr (KIND == K_ROSENBROCK) {
     const T d = z * z - zn;
