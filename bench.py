@@ -495,6 +495,11 @@ def main():
 
     wall32, per32 = timed(False)
     wall64, per64 = timed(True)
+    # measured peaks beside the nominal ones: streaming reads of the FP32 population, and the
+    # dense BF16 matrix-core rate
+    meas = {"hbm_read_gbs": c.probe_read_gbs(x32), "mfma_bf16_tflops": c.probe_mfma_bf16_tflops(),
+            "how": "curob_probe_read over the 104.9 MB FP32 population (read only), curob_probe_mfma_bf16 "
+                   "(four 16x16x32 chains per wave, four waves per SIMD); fastest of the timed launches"}
     c.dispose()
     if args.copy_probe:
         # a plain streaming kernel of known traffic (reads and writes the FP32 population once),
@@ -539,7 +544,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "kernel": resident_key(dom),
                      "function": NAMES[dom], "algorithmic_bytes_per_launch": bytes32,
-                     "avg_launch_ms": per32[dom]},
+                     "avg_launch_ms": per32[dom], "measured_peak": meas,
+                     "frac_of_measured_read": ach / meas["hbm_read_gbs"]},
         "fp64_path": {"value": evals * args.steps / wall64, "unit": "evals/s", "ms_per_step": ms64,
                       "split_over_fp64": (evals * args.steps / wall32) / (evals * args.steps / wall64)},
         "per_function": per_fn,

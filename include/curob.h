@@ -173,6 +173,20 @@ int curob_batch_tune(curob_batch *b, int reps, float *best_us);
 /* Frees a batch (after waiting for the library stream).  NULL is ignored. */
 int curob_batch_destroy(curob_batch *b);
 
+/* ---- Measured peaks (for benchmarks that report a roofline) ---------------------------------
+ * Not part of the evaluation interface: callers are benchmarks that state a measured peak
+ * beside the nominal one.  Both run on the library stream, wait for it, and report the
+ * fastest of `reps` timed launches (one untimed warm-up first).  Need an initialised library
+ * (CUROB_E_STATE otherwise); they allocate and free a 16-byte device buffer per call.
+ *
+ * curob_probe_read: reads every 16-byte word of the device buffer d_buf (bytes: a positive
+ *   multiple of 16, d_buf 16-byte aligned, else CUROB_E_ARG) once per launch on a grid of
+ *   8 workgroups per CU; *gbs = bytes / time in GB/s.  The buffer is only read.
+ * curob_probe_mfma_bf16: four 4-wave workgroups per CU each issue 4 x 4096 dense 16x16x32
+ *   BF16 MFMAs per wave in four independent chains; *tflops = 16384 flops x MFMAs / time. */
+int curob_probe_read(const void *d_buf, unsigned long long bytes, int reps, double *gbs);
+int curob_probe_mfma_bf16(int reps, double *tflops);
+
 #ifdef __cplusplus
 }
 #endif

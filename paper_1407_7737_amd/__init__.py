@@ -157,6 +157,20 @@ def generate_basic(fid: int, dim: int, seed: int):
     return o, R
 
 
+def probe_read_gbs(x, reps: int = 10) -> float:
+    """Measured streaming read bandwidth (GB/s) over the device tensor x (curob_probe_read)."""
+    gbs = ctypes.c_double()
+    check(lib.curob_probe_read(_ptr(x), int(x.numel() * x.element_size()), int(reps), ctypes.byref(gbs)))
+    return gbs.value
+
+
+def probe_mfma_bf16_tflops(reps: int = 5) -> float:
+    """Measured dense BF16 16x16x32 MFMA rate (TFLOP/s) (curob_probe_mfma_bf16)."""
+    tf = ctypes.c_double()
+    check(lib.curob_probe_mfma_bf16(int(reps), ctypes.byref(tf)))
+    return tf.value
+
+
 class Batch:
     """Populations of uneven size, dimension and function evaluated by one persistent launch
     replayed as a HIP graph (curob_batch_*).  Population i is Tab. 1 function fids[i] at

@@ -31,6 +31,7 @@ EXPORTED = [
     "curob_define_composition", "curob_last_error", "curob_get_problem", "curob_generate_basic",
     "curob_batch_create", "curob_batch_bind", "curob_batch_run", "curob_batch_run_direct",
     "curob_batch_configure", "curob_batch_shape", "curob_batch_tune", "curob_batch_destroy",
+    "curob_probe_read", "curob_probe_mfma_bf16",
 ]
 BATCH_KEY_BASE = 2048  # population i of a batch keys its random data like custom id 2048 + i
 
@@ -70,6 +71,8 @@ def _load():
         "curob_batch_shape": (i32, [vp, ip, ip, ip, ip]),
         "curob_batch_tune": (i32, [vp, i32, ctypes.POINTER(ctypes.c_float)]),
         "curob_batch_destroy": (i32, [vp]),
+        "curob_probe_read": (i32, [vp, u64, i32, ctypes.POINTER(ctypes.c_double)]),
+        "curob_probe_mfma_bf16": (i32, [i32, ctypes.POINTER(ctypes.c_double)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)

@@ -21,7 +21,7 @@ def curob():
 def declared_functions():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    names = re.findall(r"^\s*(?:const\s+)?[a-z_]+\s*\*?\s*([a-z_]+)\s*\(", src, flags=re.M)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_]+\s*\*?\s*([a-z_][a-z0-9_]*)\s*\(", src, flags=re.M)
     return sorted(set(names))
 
 
@@ -46,6 +46,9 @@ def test_calls_before_initialize_report_state(curob):
     assert lib.func_evaluatef(0, None, 10, None) == curob.CUROB_E_STATE
     assert lib.h_func_evaluate(0, None, 1, None) == curob.CUROB_E_STATE
     assert lib.curob_set_mode(0) == curob.CUROB_E_STATE
+    out = ctypes.c_double()
+    assert lib.curob_probe_read(None, 16, 1, ctypes.byref(out)) == curob.CUROB_E_STATE
+    assert lib.curob_probe_mfma_bf16(1, ctypes.byref(out)) == curob.CUROB_E_STATE
     assert lib.dispose() == curob.CUROB_E_STATE
     assert "not initialised" in curob.last_error() or "nothing to dispose" in curob.last_error()
 
