@@ -74,22 +74,6 @@ __device__ __forceinline__ int frag_pos(int q, int e) {
   else return 4 * q + e;
 }
 
-// The formula of a runtime family id (hybrid segments): one switch per call site.
-template <typename T>
-__device__ __forceinline__ void phi_any(int kind, T (&v)[3], T &p, T z, T zn, T coef, T prm) {
-  switch (kind) {
-#define CUROB_PHI_CASE(K) \
-  case K: phi<K, T>(v, p, z, zn, coef, prm); break;
-    CUROB_PHI_CASE(K_WSPHERE) CUROB_PHI_CASE(K_POWERS) CUROB_PHI_CASE(K_SHARPV) CUROB_PHI_CASE(K_STEP)
-    CUROB_PHI_CASE(K_WEIERSTRASS) CUROB_PHI_CASE(K_GRIEWANK) CUROB_PHI_CASE(K_RASTRIGIN) CUROB_PHI_CASE(K_F7)
-    CUROB_PHI_CASE(K_GRIEROSEN) CUROB_PHI_CASE(K_ROSENBROCK) CUROB_PHI_CASE(K_SCHWEFEL) CUROB_PHI_CASE(K_KATSUURA)
-    CUROB_PHI_CASE(K_LUNACEK) CUROB_PHI_CASE(K_ACKLEY) CUROB_PHI_CASE(K_HAPPYCAT) CUROB_PHI_CASE(K_HGBAT)
-    CUROB_PHI_CASE(K_F6)
-#undef CUROB_PHI_CASE
-    default: break;
-  }
-}
-
 template <typename T>
 __device__ __forceinline__ T finalize_any(int kind, const T (&s)[3], T p, int n) {
   switch (kind) {
@@ -571,22 +555,41 @@ __global__ __launch_bounds__(256) void k_rowwise(TiledProb tp, const typename Ty
   Acc<T> a;
   a.init();
   for (int j0 = 0; j0 < D; j0 += 256) {
+    // every load of the step is issued before the first use (indices past the row are clamped
+    // and their terms masked), so the step waits for memory once
+    T xv[4], ov[4], cv[4], fv[4], xn[4], on[4], cn[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = j0 + 64 * u + lane;
+      const int jc = j < D ? j : D - 1;
+      xv[u] = xr[jc];
+      ov[u] = oh[jc];
+      cv[u] = cz[jc];
+      fv[u] = KT_::needs_coef || KT_::pairwise ? coef[jc] : T(0);
+      if constexpr (KT_::pairwise) {
+        const int jn = jc + 1 < D ? jc + 1 : 0;
+        xn[u] = xr[jn];
+        on[u] = oh[jn];
+        cn[u] = cz[jn];
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
     T v[3] = {T(0), T(0), T(0)};
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int j = j0 + 64 * u + lane;
       if (j < D) {
-        const T z = s * (xr[j] - oh[j]) + cz[j];
+        const T z = s * (xv[u] - ov[u]) + cv[u];
         if constexpr (KT_::pairwise) {
-          const int jn = j + 1 < D ? j + 1 : (kind_pair_wraps_c(KIND) ? 0 : -1);
-          if (jn >= 0) {
-            const T zn = s * (xr[jn] - oh[jn]) + cz[jn];
+          // the last variable pairs with the first only for the wrapping families
+          if (j + 1 < D || kind_pair_wraps_c(KIND)) {
+            const T zn = s * (xn[u] - on[u]) + cn[u];
             T w[3] = {T(0), T(0), T(0)};
-            phi<KIND, T>(w, a.p, z, zn, coef[j], prm);
+            phi<KIND, T>(w, a.p, z, zn, fv[u], prm);
             v[0] += w[0];
           }
         } else {
-          phi<KIND, T>(v, a.p, z, T(0), KT_::needs_coef ? coef[j] : T(0), prm);
+          phi<KIND, T>(v, a.p, z, T(0), fv[u], prm);
         }
       }
     }
@@ -646,6 +649,40 @@ __global__ __launch_bounds__(256) void k_tiled_finalize(TiledProb tp, const type
   if (live) out[row] = F + T(tp.bias);
 }
 
+// Pair terms of one pairwise segment for one row (z in zr, padded order), lanes over the
+// positions, two per lane per step: the table and z loads of a step are issued together
+// (positions past the segment are clamped and masked), then the formula of family K.
+template <int K, typename T>
+__device__ __forceinline__ void pair_terms(const TiledProb &tp, const TiledSeg &sg, const T *zr, const T *coefp, T prm,
+                                           int lane, Acc<T> &a) {
+  for (int p0 = sg.p0; p0 < sg.p1; p0 += 128) {
+    int pc[2], sp[2], gi[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int pp = p0 + 64 * u + lane;
+      pc[u] = pp < sg.p1 ? pp : sg.p1 - 1;
+      sp[u] = tp.succ[pc[u]];
+      gi[u] = tp.gidx[pc[u]];
+    }
+    T z[2], zn[2], cf[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      z[u] = zr[pc[u]];
+      zn[u] = zr[sp[u] >= 0 ? sp[u] : pc[u]];
+      cf[u] = coefp[pc[u]];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      if (p0 + 64 * u + lane < sg.p1 && gi[u] >= 0 && sp[u] >= 0) {
+        T v[3] = {T(0), T(0), T(0)};
+        phi<K, T>(v, a.p, z[u], zn[u], cf[u], prm);
+        a.add(0, v[0]);
+      }
+    }
+  }
+}
+
 // Problems with pair terms: one wave per row, lanes over the output groups and the pair
 // positions of the row.
 template <int P>
@@ -665,13 +702,12 @@ __global__ __launch_bounds__(256) void k_tiled_finalize_pairs(TiledProb tp, cons
     if (sg.pairwise) {
       const T prm = param_any<T>(sg.kind, sg.n, sg.kparam);
       const T *zr = zbuf + static_cast<size_t>(row) * tp.Dp;
-      for (int pp = sg.p0 + lane; pp < sg.p1; pp += 64) {
-        const int sp = tp.succ[pp];
-        if (tp.gidx[pp] >= 0 && sp >= 0) {
-          T v[3] = {T(0), T(0), T(0)};
-          phi_any<T>(sg.kind, v, a.p, zr[pp], zr[sp], coefp[pp], prm);
-          a.add(0, v[0]);
-        }
+      switch (sg.kind) {
+#define CUROB_PAIR_CASE(K) \
+  case K: pair_terms<K, T>(tp, sg, zr, coefp, prm, lane, a); break;
+        CUROB_PAIR_CASE(K_F7) CUROB_PAIR_CASE(K_GRIEROSEN) CUROB_PAIR_CASE(K_ROSENBROCK) CUROB_PAIR_CASE(K_F6)
+#undef CUROB_PAIR_CASE
+        default: break;
       }
 #pragma unroll
       for (int sh = 1; sh < 64; sh <<= 1) {
