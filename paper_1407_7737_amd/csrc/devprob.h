@@ -32,19 +32,21 @@ inline constexpr int kw_of(int path) { return is_split(path) ? 32 : 4; }
 inline constexpr int blocks_of(int) { return 1; }
 
 struct DevProb {
-  // every pointer is device memory owned by the library
-  const void *oh;        // shift rounded to the path's type: original variable order (D entries),
-                         // or on the split paths packed order (max(KT*KW, 16*MT) entries, zeros
-                         // past D)
-  const uint16_t *goff;  // packed position -> byte offset of its variable in an LDS row; KT*KW
-                         // entries, padding -> the zero slot at D
-  const void *cz;        // per packed position (16*MT entries) offset c' added after the rotation:
-                         // c minus the rotated, scaled rounding error of the shift on FP32 paths
-  const void *coef;      // per packed position coefficient (elliptic weights, 1/sqrt(i), ...)
-  const int16_t *succ;   // per packed position: packed position of the formula successor or -1
-  const void *qfrag;     // nonzero tiles of s*Qp in MFMA operand order (path-specific layout)
-  const int *mtab;       // per m-tile: first k-tile, last k-tile, first tile index and, on the
-                         // split paths, 4 * first k-tile + (last - first) (0 elsewhere)
+  // The per-problem tables, laid out exactly as the fixed part of the kernel's LDS carve
+  // (kernels.h lds_layout), in one device block the kernel copies with a single pass:
+  //   rotation tiles: nonzero tiles of s*Qp in MFMA operand order (path-specific layout);
+  //   gather offsets: packed position -> byte offset of its variable in an LDS row (KT*KW
+  //     entries, padding -> the zero slot at D);
+  //   o_hi: the shift rounded to the path's type, original variable order (D entries), or on
+  //     the split paths packed order (max(KT*KW, 16*MT) entries, zeros past D);
+  //   c': per packed position (16*MT entries), c minus the rotated, scaled rounding error of the
+  //     shift on the FP32 paths;
+  //   coefficients per packed position (elliptic weights, 1/sqrt(i), ...);
+  //   successors: per packed position the packed position of the formula successor or -1;
+  //   k ranges: per m-tile first k-tile, last k-tile, first tile index and, on the split paths,
+  //     4 * first k-tile + (last - first).
+  const void *image;  // device memory owned by the library
+  int image_bytes;    // the fixed part of the LDS carve, a multiple of 16
   int D;                 // dimension
   int S;                 // LDS row stride in elements (4*odd, >= D+1 and >= 16*MT)
   int KT;                // k-tiles

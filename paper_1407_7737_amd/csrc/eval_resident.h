@@ -67,10 +67,26 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ void copy_to_lds(unsigned char *dst, const void *src, int bytes) {
+// Copies the problem's table image (bytes, a multiple of 16, laid out as the fixed part of
+// the LDS carve) to the start of LDS: each thread issues the loads of up to four 16-byte words
+// (clamped indices, no branch around a load) before storing them, one round trip per round.
+__device__ __forceinline__ void copy_image(unsigned char *dst, const void *src, int bytes) {
   const int4 *s = reinterpret_cast<const int4 *>(src);
   int4 *d = reinterpret_cast<int4 *>(dst);
-  for (int i = threadIdx.x; i < (bytes >> 4); i += blockDim.x) d[i] = s[i];
+  const int n = bytes >> 4;
+  for (int base = threadIdx.x; base < n; base += 4 * blockDim.x) {
+    int4 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = base + u * blockDim.x;
+      v[u] = s[i < n ? i : n - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = base + u * blockDim.x;
+      if (i < n) d[i] = v[u];
+    }
+  }
 }
 
 // Buffer resource over rows [row0, n) of x: loads past the end return zeros instead of
@@ -406,17 +422,9 @@ __device__ __forceinline__ void resident_eval(const DevProb &pb, const typename 
   if (g < gend) xt.load(rows_rsrc(x, g * ROWS, n, D), nload, lane);
   T *Y = reinterpret_cast<T *>(smem + L.y + wave * L.slice_bytes);
   if (setup) {
-    if (ROT) {
-      copy_to_lds(smem + L.q, pb.qfrag, L.q_bytes);
-      copy_to_lds(smem + L.goff, pb.goff, L.goff_bytes);
-      // the k ranges go to LDS too: read from global memory inside the loop, their vector-memory
-      // wait would also wait for the next row group's prefetch
-      copy_to_lds(smem + L.mtab, pb.mtab, L.mtab_bytes);
-    }
-    copy_to_lds(smem + L.oh, pb.oh, L.vec_bytes);
-    copy_to_lds(smem + L.cz, pb.cz, L.mp_bytes);
-    if (KT_::needs_coef) copy_to_lds(smem + L.coef, pb.coef, L.mp_bytes);
-    if (KT_::pairwise) copy_to_lds(smem + L.succ, pb.succ, L.succ_bytes);
+    // every table (the k ranges included: read from global memory inside the loop, their
+    // vector-memory wait would also wait for the next row group's prefetch) in one pass
+    copy_image(smem, pb.image, pb.image_bytes);
     // columns D..S-1 of every row are zero: the gather's padding slot and the unrotated read-out
     for (int i = lane; i < ROWS * (S - D); i += 64) Y[(i / (S - D)) * S + D + i % (S - D)] = T(0);
     __syncthreads();

@@ -155,8 +155,24 @@ __global__ __launch_bounds__(256) void k_tiled_pack(TiledProb tp, const typename
   T *s_x = reinterpret_cast<T *>(smem + round16(tp.Dp * 4) + round16(D * static_cast<int>(sizeof(T))));
   const int row0 = blockIdx.x * R;  // rows [row0, row0 + R) lie in one row tile
   const int nvalid = n - row0 < 0 ? 0 : (n - row0 < R ? n - row0 : R);
-  for (int i = threadIdx.x; i < tp.Dp; i += 256) s_gidx[i] = tp.gidx[i];
-  for (int i = threadIdx.x; i < D; i += 256) s_oh[i] = reinterpret_cast<const T *>(tp.oh)[i];
+  // position tables: a thread's loads of a round are issued before its stores (clamped
+  // indices, no branch around a load), so the copy costs one memory round trip per round
+  for (int base = threadIdx.x; base < tp.Dp; base += 256 * 4) {
+    int g[4];
+    T oh4[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = base + 256 * u;
+      g[u] = tp.gidx[i < tp.Dp ? i : tp.Dp - 1];
+      oh4[u] = reinterpret_cast<const T *>(tp.oh)[i < D ? i : D - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = base + 256 * u;
+      if (i < tp.Dp) s_gidx[i] = g[u];
+      if (i < D) s_oh[i] = oh4[u];
+    }
+  }
   // stage the rows at stride SX (the 16 rows of a tile fall in distinct LDS banks); all of a
   // thread's loads are issued before any store so many requests are in flight
   constexpr int U = 16;

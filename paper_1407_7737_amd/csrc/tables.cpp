@@ -5,6 +5,7 @@
 // (pre-scaled by the function's s) tile by tile, skipping tiles that are all zero.
 #include "tables.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -307,15 +308,23 @@ hipError_t upload_tables(const HostTables &ht, DevTables &dt) {
     *dst = d;
     return e;
   };
+  // one block in the kernel's LDS order: the setup copies it with a single pass
   DevProb pb = ht.pb;
-  hipError_t e;
-  if ((e = up(ht.oh.data(), ht.oh.size(), &pb.oh)) != hipSuccess) return e;
-  if ((e = up(ht.goff.data(), ht.goff.size() * 2, reinterpret_cast<const void **>(&pb.goff))) != hipSuccess) return e;
-  if ((e = up(ht.cz.data(), ht.cz.size(), &pb.cz)) != hipSuccess) return e;
-  if ((e = up(ht.coef.data(), ht.coef.size(), &pb.coef)) != hipSuccess) return e;
-  if ((e = up(ht.succ.data(), ht.succ.size() * 2, reinterpret_cast<const void **>(&pb.succ))) != hipSuccess) return e;
-  if ((e = up(ht.qfrag.data(), ht.qfrag.size(), &pb.qfrag)) != hipSuccess) return e;
-  if ((e = up(ht.mtab.data(), ht.mtab.size() * 4, reinterpret_cast<const void **>(&pb.mtab))) != hipSuccess) return e;
+  const LdsLayout L = lds_layout(ht.path, pb, 1);
+  std::vector<unsigned char> img(static_cast<size_t>(L.fixed), 0);
+  auto place = [&](int off, int cap, const void *src, size_t bytes) {
+    if (cap > 0 && bytes > 0) std::memcpy(img.data() + off, src, std::min(bytes, static_cast<size_t>(cap)));
+  };
+  place(L.q, L.q_bytes, ht.qfrag.data(), ht.qfrag.size());
+  place(L.goff, L.goff_bytes, ht.goff.data(), ht.goff.size() * 2);
+  place(L.oh, L.vec_bytes, ht.oh.data(), ht.oh.size());
+  place(L.cz, L.mp_bytes, ht.cz.data(), ht.cz.size());
+  place(L.coef, L.mp_bytes, ht.coef.data(), ht.coef.size());
+  place(L.succ, L.succ_bytes, ht.succ.data(), ht.succ.size() * 2);
+  place(L.mtab, L.mtab_bytes, ht.mtab.data(), ht.mtab.size() * 4);
+  hipError_t e = up(img.data(), img.size(), &pb.image);
+  if (e != hipSuccess) return e;
+  pb.image_bytes = L.fixed;
   dt.pb = pb;
   dt.ready = true;
   return hipSuccess;
