@@ -133,12 +133,50 @@ struct XTile {
     }
   }
 
+  // stage with the shift vectors read first, all together; stores past nload reach the spill
+  // row only (the registers beyond the row group's loads hold values never used)
+  __device__ __forceinline__ void stage_batched(int D, int S, T *Y, const T *oh, int lane) const {
+    const int e0 = lane * NV;
+    constexpr int step = 64 * NV;
+    const int dr = step / D, dj = step - dr * D;
+    L o[CMAX];
+    {
+      int jj = e0 % D;
+#pragma unroll
+      for (int t = 0; t < CMAX; ++t) {
+        if constexpr (VEC) o[t] = *reinterpret_cast<const V *>(oh + jj);
+        else o[t] = oh[jj];
+        jj += dj;
+        jj = jj >= D ? jj - D : jj;
+      }
+    }
+    int rr = e0 / D, jj = e0 - rr * D;
+#pragma unroll
+    for (int t = 0; t < CMAX; ++t) {
+      const int ra = rr < ROWS ? rr : ROWS;
+      if constexpr (VEC) *reinterpret_cast<V *>(Y + ra * S + jj) = v[t] - o[t];
+      else Y[ra * S + jj] = v[t] - o[t];
+      jj += dj;
+      rr += dr;
+      if (jj >= D) {
+        jj -= D;
+        ++rr;
+      }
+    }
+  }
+
   // Y[r][j] = x[r][j] - o_hi[j] (RAW: x[r][j]; the split paths subtract o_hi later, in packed
   // order) for the wave's rows; elements past the last row land in the spill row ROWS of the
   // slice.  RAW stores need neither a shift read nor a guard: registers past nload hold zeros
   // and only reach the spill row.
   template <bool RAW>
   __device__ __forceinline__ void stage(int nload, int D, int S, T *Y, const T *oh, int lane) const {
+    if constexpr (!RAW && sizeof(T) == 8) {
+      // FP64 (two waves per SIMD, registers to spare): every shift read is issued before the
+      // first subtraction, one LDS round trip instead of one per load
+      stage_batched(D, S, Y, oh, lane);
+      return;
+    }
     const int e0 = lane * NV;
     int rr = e0 / D, jj = e0 - rr * D;
     constexpr int step = 64 * NV;
@@ -418,7 +456,7 @@ __device__ __forceinline__ void resident_eval(const DevProb &pb, const typename 
 
   // the first row group's loads go out before the tables are copied
   Tile xt;
-  if constexpr (is_split(P)) xt.clear();
+  if constexpr (is_split(P) || P == PATH_F64) xt.clear();
   if (g < gend) xt.load(rows_rsrc(x, g * ROWS, n, D), nload, lane);
   T *Y = reinterpret_cast<T *>(smem + L.y + wave * L.slice_bytes);
   if (setup) {
