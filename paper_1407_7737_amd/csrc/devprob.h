@@ -48,7 +48,8 @@ struct DevProb {
   const void *image;  // device memory owned by the library
   int image_bytes;    // the fixed part of the LDS carve, a multiple of 16
   int D;                 // dimension
-  int S;                 // LDS row stride in elements (4*odd, >= D+1 and >= 16*MT)
+  int S;                 // LDS row stride in elements (4*odd, >= D+1, and >= 16*MT unless the rows
+                         // are loaded directly, kernels.h direct_rows)
   int KT;                // k-tiles
   int MT;                // m-tiles
   int ntiles;            // nonzero tiles

@@ -34,7 +34,8 @@ LaunchShape resident_shape(int path, const DevProb &pb, int n, int num_cu) {
   const LdsLayout one = lds_layout(path, pb, 1);
   const int slice = one.total - one.fixed;
   int waves = (kMaxLdsBytes - one.fixed) / slice;
-  if (waves > max_waves_of(path)) waves = max_waves_of(path);
+  const int wmax = max_waves_of(path, direct_rows(path, pb.rotated, pb.kind));
+  if (waves > wmax) waves = wmax;
   if (waves < 1) waves = 1;
   const int rows = kRowsPerBlock * blocks_of(path);
   const int groups = (n + rows - 1) / rows;

@@ -1,11 +1,13 @@
 // eval_resident.h -- fused evaluation kernel for basic functions of dimension <= 128.
 //
 // Each wave evaluates 16 candidate rows per iteration and loops over row groups (grid-stride):
-//   1. stage   the rows' x (contiguous in HBM) arrived in registers during the previous
-//              iteration through bounds-checked buffer loads; they go to the wave's LDS slice
-//              (the FP32/FP64-MFMA paths store y = x - o_hi, the split paths store x and
-//              subtract o_hi in the gather), and the loads of the next row group are issued at
-//              once so that HBM traffic overlaps everything below;
+//   1. stage   the rows' x (contiguous in HBM) reach the wave's LDS slice through
+//              bounds-checked buffer loads issued one iteration ahead, so that HBM traffic
+//              overlaps everything below.  Rotated non-pairwise problems on the split paths load
+//              straight into the slice (buffer loads that write LDS, issued as soon as the
+//              gather has read the previous group); the others hold the rows in registers and
+//              store them (the FP32/FP64-MFMA paths store y = x - o_hi, the split paths store x
+//              and subtract o_hi in the gather);
 //   2. rotate  Z^T = (s Qp) Y^T on the matrix cores over the nonzero tiles of the packed
 //              block-diagonal rotation (Sec. 1.2: three random variable groups, one orthonormal
 //              block each).  The B operand is gathered from LDS in group order; on the split
@@ -98,6 +100,38 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t rows_rsrc(const T *x, int row0
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(x + static_cast<size_t>(row0) * D), (short)0, nb,
                                            0x00020000);
 }
+
+// Loads a row group straight into the wave's LDS slice (buffer loads that write LDS; no
+// register holds the data): row r of the group, 4D bytes from byte 4rD of the resource, lands at
+// Y + rS.  16-byte loads when every row starts 16-byte aligned in memory, 4-byte loads
+// otherwise; lanes past a row's length are masked off, so nothing is written past column D - 1.
+// The wave must wait for the vector-memory counter before reading the slice.
+__device__ __forceinline__ void load_rows_direct(__amdgpu_buffer_rsrc_t rs, int D, int S, float *Y, bool wide,
+                                                 int lane) {
+  typedef __attribute__((address_space(3))) void *lds_ptr;
+  if (wide) {
+    if (lane < (D >> 2)) {
+#pragma unroll
+      for (int r = 0; r < kRowsPerBlock; ++r)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_ptr)(Y + r * S), 16, lane * 16, r * 4 * D, 0, 0);
+    }
+  } else {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (lane + 64 * h < D) {
+#pragma unroll
+        for (int r = 0; r < kRowsPerBlock; ++r)
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_ptr)(Y + r * S + 64 * h), 4, (lane + 64 * h) * 4, r * 4 * D,
+                                                   0, 0);
+      }
+    }
+  }
+}
+
+// s_waitcnt operands (gfx9 encoding): wait for every vector-memory operation, or for every
+// LDS operation, leaving the other counters free.
+constexpr int kWaitVmem = 0x3F70;
+constexpr int kWaitLds = 0xC07F;
 
 // Registers holding a wave's rows between their load and their staging: 16-byte loads when
 // the dimension is a multiple of the vector width (VEC), element loads otherwise.
@@ -233,10 +267,32 @@ struct RotOps<PATH_F64> {
   using Frag = double;
 };
 
+// Cuts two gathered elements y (positions e, e + 1 of k-tile kt) into the split path's bf16
+// terms: y - hi and the next residual are exact in FP32.
+template <int P>
+__device__ __forceinline__ void cut_terms(typename RotOps<P>::Frag (&bf)[RotOps<P>::NTERM][blocks_of(P)][RotOps<P>::KTMAX],
+                                          int b, int kt, int e, f32x2 y) {
+  const bf16x2 h = __builtin_convertvector(y, bf16x2);
+  const f32x2 r1 = y - __builtin_convertvector(h, f32x2);
+  bf[0][b][kt][e] = h[0];
+  bf[0][b][kt][e + 1] = h[1];
+  if constexpr (RotOps<P>::NTERM == 3) {
+    const bf16x2 m = __builtin_convertvector(r1, bf16x2);
+    const bf16x2 l = __builtin_convertvector(r1 - __builtin_convertvector(m, f32x2), bf16x2);
+    bf[1][b][kt][e] = m[0];
+    bf[1][b][kt][e + 1] = m[1];
+    bf[2][b][kt][e] = l[0];
+    bf[2][b][kt][e + 1] = l[1];
+  } else {
+    const bf16x2 l = __builtin_convertvector(r1, bf16x2);
+    bf[1][b][kt][e] = l[0];
+    bf[1][b][kt][e + 1] = l[1];
+  }
+}
+
 // Gathers this lane's B operand of every k-tile and column block from the staged rows (packed
 // order via the byte offsets s_goff) and, on the split paths, subtracts o_hi (s_ohp, packed
-// order) and cuts each y into bf16 terms (y - hi and the next residual are exact in FP32).
-// Yb: row r of column block 0.
+// order) and cuts each y into bf16 terms.  Yb: row r of column block 0.
 template <int P>
 __device__ __forceinline__ void gather_b(typename RotOps<P>::Frag (&bf)[RotOps<P>::NTERM][blocks_of(P)][RotOps<P>::KTMAX],
                                          int KT, const uint16_t *s_goff, const unsigned char *Yb, int bstride,
@@ -262,22 +318,7 @@ __device__ __forceinline__ void gather_b(typename RotOps<P>::Frag (&bf)[RotOps<P
           for (int b = 0; b < NB; ++b) {
             const f32x2 y = f32x2{*reinterpret_cast<const float *>(Yb + b * bstride + o0),
                                   *reinterpret_cast<const float *>(Yb + b * bstride + o1)} - oo;
-            const bf16x2 h = __builtin_convertvector(y, bf16x2);
-            const f32x2 r1 = y - __builtin_convertvector(h, f32x2);
-            bf[0][b][kt][e] = h[0];
-            bf[0][b][kt][e + 1] = h[1];
-            if constexpr (R::NTERM == 3) {
-              const bf16x2 m = __builtin_convertvector(r1, bf16x2);
-              const bf16x2 l = __builtin_convertvector(r1 - __builtin_convertvector(m, f32x2), bf16x2);
-              bf[1][b][kt][e] = m[0];
-              bf[1][b][kt][e + 1] = m[1];
-              bf[2][b][kt][e] = l[0];
-              bf[2][b][kt][e + 1] = l[1];
-            } else {
-              const bf16x2 l = __builtin_convertvector(r1, bf16x2);
-              bf[1][b][kt][e] = l[0];
-              bf[1][b][kt][e + 1] = l[1];
-            }
+            cut_terms<P>(bf, b, kt, e, y);
           }
         }
       } else {
@@ -285,6 +326,31 @@ __device__ __forceinline__ void gather_b(typename RotOps<P>::Frag (&bf)[RotOps<P
 #pragma unroll
         for (int b = 0; b < NB; ++b)
           bf[0][b][kt] = *reinterpret_cast<const typename R::Frag *>(Yb + b * bstride + off);
+      }
+    }
+  }
+}
+
+// The same gather on a split path from addresses computed once per launch: ga holds the LDS
+// byte address (from lds) of every element this lane reads, 8 per k-tile, so a row group costs
+// no offset-table reads and no address arithmetic (one column block).
+template <int P>
+__device__ __forceinline__ void gather_pre(typename RotOps<P>::Frag (&bf)[RotOps<P>::NTERM][blocks_of(P)][RotOps<P>::KTMAX],
+                                           int KT, const uint32_t (&ga)[RotOps<P>::KTMAX * 8], const unsigned char *lds,
+                                           int q, const float *s_ohp) {
+  using R = RotOps<P>;
+#pragma unroll
+  for (int kt = 0; kt < R::KTMAX; ++kt) {
+    if (kt < KT) {
+      const f32x4 oa = *reinterpret_cast<const f32x4 *>(s_ohp + kt * 32 + q * 8);
+      const f32x4 ob = *reinterpret_cast<const f32x4 *>(s_ohp + kt * 32 + q * 8 + 4);
+      const float ov[8] = {oa[0], oa[1], oa[2], oa[3], ob[0], ob[1], ob[2], ob[3]};
+#pragma unroll
+      for (int e = 0; e < 8; e += 2) {
+        const f32x2 oo = {ov[e], ov[e + 1]};
+        const f32x2 y = f32x2{*reinterpret_cast<const float *>(lds + ga[kt * 8 + e]),
+                              *reinterpret_cast<const float *>(lds + ga[kt * 8 + e + 1])} - oo;
+        cut_terms<P>(bf, 0, kt, e, y);
       }
     }
   }
@@ -454,11 +520,18 @@ __device__ __forceinline__ void resident_eval(const DevProb &pb, const typename 
   const int r = lane & 15, q = lane >> 4;
   const int nload = (ROWS * D + 64 * Tile::NV - 1) / (64 * Tile::NV);
 
-  // the first row group's loads go out before the tables are copied
-  Tile xt;
-  if constexpr (is_split(P) || P == PATH_F64) xt.clear();
-  if (g < gend) xt.load(rows_rsrc(x, g * ROWS, n, D), nload, lane);
+  // rows loaded straight into the slice, or staged through registers
+  constexpr bool DIRECT = direct_rows(P, ROT, KIND);
   T *Y = reinterpret_cast<T *>(smem + L.y + wave * L.slice_bytes);
+  // (direct) every row starts 16-byte aligned in memory: D a multiple of 4 and x aligned
+  const bool wide = (D & 3) == 0 && (reinterpret_cast<uintptr_t>(x) & 15) == 0;
+  // staged: the first row group's loads go out before the tables are copied.  Direct: after
+  // the copy (in a batch the LDS may still hold another problem's tables until the barrier)
+  Tile xt;
+  if constexpr (!DIRECT) {
+    if constexpr (is_split(P) || P == PATH_F64) xt.clear();
+    if (g < gend) xt.load(rows_rsrc(x, g * ROWS, n, D), nload, lane);
+  }
   if (setup) {
     // every table (the k ranges included: read from global memory inside the loop, their
     // vector-memory wait would also wait for the next row group's prefetch) in one pass
@@ -467,6 +540,9 @@ __device__ __forceinline__ void resident_eval(const DevProb &pb, const typename 
     for (int i = lane; i < ROWS * (S - D); i += 64) Y[(i / (S - D)) * S + D + i % (S - D)] = T(0);
     __syncthreads();
   }
+  if constexpr (DIRECT) {
+    if (g < gend) load_rows_direct(rows_rsrc(x, g * ROWS, n, D), D, S, reinterpret_cast<float *>(Y), wide, lane);
+  }
 
   const T scale = T(pb.scale);
   const T prm = kind_param<KIND, T>(pb.Df, pb.kparam);
@@ -474,21 +550,56 @@ __device__ __forceinline__ void resident_eval(const DevProb &pb, const typename 
   const int bstride = kRowsPerBlock * S * static_cast<int>(sizeof(T));
   const int4 *s_mtab = reinterpret_cast<const int4 *>(smem + L.mtab);
 
+  // three-product direct path: the gather addresses are fixed for the launch and fit the
+  // registers the staged rows would have used (the six-product path has no room for them)
+  constexpr bool PRE = DIRECT && P == PATH_SPLIT;
+  uint32_t ga[RotOps<P>::KTMAX * 8];
+  if constexpr (PRE) {
+    const uint32_t ybase = static_cast<uint32_t>(reinterpret_cast<const unsigned char *>(Y + r * S) - smem);
+#pragma unroll
+    for (int kt = 0; kt < RotOps<P>::KTMAX; ++kt) {
+      const uint4 idx = *reinterpret_cast<const uint4 *>(s_goff + (kt < pb.KT ? kt : 0) * 32 + q * 8);
+      const uint32_t iw[4] = {idx.x, idx.y, idx.z, idx.w};
+#pragma unroll
+      for (int e = 0; e < 8; e += 2) {
+        ga[kt * 8 + e] = ybase + (iw[e >> 1] & 0xFFFFu);
+        ga[kt * 8 + e + 1] = ybase + (iw[e >> 1] >> 16);
+      }
+    }
+  }
+  // (direct) the result of the previous row group, stored once the next group's rows have
+  // been requested: its store then never delays the wait for those rows
+  T pend = T(0);
+  int prow = n;
   for (; g < gend; g += gstride) {
     const int row0 = g * ROWS;
-    wave_sync();
-    xt.template stage<is_split(P)>(nload, D, S, Y, s_oh, lane);
-    // the next row group's loads are in flight during everything below
     const int gn = g + gstride;
-    if (gn < gend) xt.load(rows_rsrc(x, gn * ROWS, n, D), nload, lane);
-    wave_sync();
+    if constexpr (DIRECT) {
+      // the row group's loads, issued one iteration earlier, have landed in the slice
+      __builtin_amdgcn_s_waitcnt(kWaitVmem);
+      wave_sync();
+    } else {
+      wave_sync();
+      xt.template stage<is_split(P)>(nload, D, S, Y, s_oh, lane);
+      // the next row group's loads are in flight during everything below
+      if (gn < gend) xt.load(rows_rsrc(x, gn * ROWS, n, D), nload, lane);
+      wave_sync();
+    }
 
     // 4-wide paths without pairwise z exchange read B from the rows in the m-tile loop
     constexpr bool SB = ROT && !is_split(P) && !KT_::pairwise && NB == 1;
     typename R::Frag bf[R::NTERM][NB][R::KTMAX];
     if constexpr (ROT && !SB) {
-      gather_b<P>(bf, pb.KT, s_goff, Yb, bstride, q, reinterpret_cast<const float *>(s_oh));
+      if constexpr (PRE) gather_pre<P>(bf, pb.KT, ga, smem, q, reinterpret_cast<const float *>(s_oh));
+      else gather_b<P>(bf, pb.KT, s_goff, Yb, bstride, q, reinterpret_cast<const float *>(s_oh));
       if constexpr (KT_::pairwise) wave_sync();  // the rows are overwritten with z below
+    }
+    if constexpr (DIRECT) {
+      // the gather's reads of the slice are complete before the next group's rows overwrite it
+      __builtin_amdgcn_s_waitcnt(kWaitLds);
+      wave_sync();
+      if (gn < gend) load_rows_direct(rows_rsrc(x, gn * ROWS, n, D), D, S, reinterpret_cast<float *>(Y), wide, lane);
+      if (q == 0 && prow < n) out[prow] = pend;
     }
     auto rotate_m = [&](Acc4 (&acc)[NB], int mm) {
       const int4 mv = s_mtab[mm];
@@ -628,7 +739,13 @@ __device__ __forceinline__ void resident_eval(const DevProb &pb, const typename 
         if constexpr (KT_::has_product) a[b].p *= __shfl_xor(a[b].p, sh, 64);
       }
       const int row = row0 + b * kRowsPerBlock + r;
-      if (q == 0 && row < n) {
+      if constexpr (DIRECT) {
+        T s[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) s[k] = a[b].get(k) - T(pb.padc[k]);
+        pend = finalize<KIND, T>(s, a[b].p, pb.Df) + T(pb.bias);
+        prow = row;
+      } else if (q == 0 && row < n) {
         T s[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) s[k] = a[b].get(k) - T(pb.padc[k]);
@@ -636,10 +753,13 @@ __device__ __forceinline__ void resident_eval(const DevProb &pb, const typename 
       }
     }
   }
+  if constexpr (DIRECT) {
+    if (q == 0 && prow < n) out[prow] = pend;
+  }
 }
 
 template <int P, int KIND, int ROT, int VEC>
-__global__ __launch_bounds__(64 * max_waves_of(P)) void k_eval_resident(DevProb pb, const typename PathT<P>::T *__restrict__ x,
+__global__ __launch_bounds__(64 * max_waves_of(P, direct_rows(P, ROT, KIND))) void k_eval_resident(DevProb pb, const typename PathT<P>::T *__restrict__ x,
                                                        typename PathT<P>::T *__restrict__ out, int n) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int nwaves = blockDim.x >> 6;

@@ -7,6 +7,7 @@
 #include <cstddef>
 
 #include "devprob.h"
+#include "problem.h"
 
 namespace curob {
 
@@ -20,17 +21,27 @@ struct LdsLayout {
 __host__ __device__ inline int round16(int b) { return (b + 15) & ~15; }
 
 constexpr int kMaxLdsBytes = 160 * 1024;  // LDS per workgroup on gfx950
+
+// Rotated problems on the split paths whose formula reads no successor take their rows from
+// memory straight into the wave's LDS slice (buffer loads that write LDS): no registers hold the
+// rows on the way, and the slice needs no spill row.  The pairwise families write z back into
+// the slice, so they stage through registers.
+__host__ __device__ constexpr bool direct_rows(int path, int rotated, int kind) {
+  return is_split(path) && rotated != 0 && kind != K_F7 && kind != K_GRIEROSEN && kind != K_ROSENBROCK &&
+         kind != K_F6;
+}
+
 // Waves per workgroup of the resident kernel: one 16-row column block per wave, so the per-wave
-// LDS slice is small and up to four waves share a SIMD on the three-product path (<= 128 VGPRs);
-// the six-product path holds a third B term (<= 168 VGPRs, three waves per SIMD) and the FP64
-// path is bound by LDS to about eight waves.
-__host__ __device__ constexpr int max_waves_of(int path) {
-  return path == PATH_F64 ? 8 : (path == PATH_SPLIT6 ? 12 : 16);
+// LDS slice is small and up to four waves share a SIMD (<= 128 VGPRs) on the split paths; the
+// six-product path holds a third B term, so with rows staged through registers it keeps three
+// waves per SIMD (<= 168 VGPRs).  The FP64 path is bound by LDS to about eight waves.
+__host__ __device__ constexpr int max_waves_of(int path, bool direct) {
+  return path == PATH_F64 ? 8 : (path == PATH_SPLIT6 && !direct ? 12 : 16);
 }
 
 // LDS carve of the resident kernel: rotation tiles, gather offsets, per-variable shift,
 // per-position tables, the per-m-tile k ranges, then one slice per wave holding its rows (16 per
-// column block) plus one spill row, S elements each.
+// column block) plus, when the rows are staged through registers, one spill row, S elements each.
 __host__ __device__ inline LdsLayout lds_layout(int path, const DevProb &pb, int nwaves) {
   const int esz = path == PATH_F64 ? 8 : 4;
   const int kw = kw_of(path);
@@ -45,7 +56,7 @@ __host__ __device__ inline LdsLayout lds_layout(int path, const DevProb &pb, int
   L.mp_bytes = round16(16 * pb.MT * esz);
   L.succ_bytes = round16(16 * pb.MT * 2);
   L.mtab_bytes = pb.rotated ? 16 * pb.MT : 0;
-  L.slice_bytes = round16((rows + 1) * pb.S * esz);
+  L.slice_bytes = round16((rows + (direct_rows(path, pb.rotated, pb.kind) ? 0 : 1)) * pb.S * esz);
   int off = 0;
   L.q = off;
   off += L.q_bytes;

@@ -269,7 +269,9 @@ bool build_host_tables(const Problem &p, int path, HostTables &ht, std::string &
 
   DevProb &pb = ht.pb;
   pb.D = D;
-  pb.S = lds_stride(D, Mp);
+  // the unrotated read-out and the pairwise z exchange reach position 16 MT - 1 of a row; rows
+  // loaded directly are only gathered from (positions < D and the zero slot at D)
+  pb.S = lds_stride(D, direct_rows(path, rotate ? 1 : 0, kind) ? 0 : Mp);
   pb.KT = KT;
   pb.MT = MT;
   pb.ntiles = ntiles;

@@ -147,6 +147,28 @@ def test_ragged_row_counts(env, n):
             assert rel_err(f[m], p(x32w)).max() <= TOL32
 
 
+@pytest.mark.parametrize("dim", [97, 100, 128])
+def test_rows_not_16_byte_aligned(env, dim):
+    """Rows that do not start 16-byte aligned (a population one float into its buffer, or
+    D not a multiple of 4) take the resident kernel's 4-byte loads; D > 64 needs two load
+    instructions per row."""
+    c, orc, torch, use = env
+    use(dim)
+    from paper_1407_7737_amd.inputs import population
+    n = 333  # 20 full groups of 16 rows and a ragged tail of 13
+    for fid in (11, 14, 16, 19):  # direct loads (x3 and x6) and the staged pairwise path
+        say(f"[unaligned] dim={dim} fid={fid} n={n}")
+        p = orc.basic(fid, dim, SEED)
+        x32 = population(n, dim, seed=dim + fid).astype(np.float32)
+        buf = torch.zeros(n * dim + 1, dtype=torch.float32, device="cuda")
+        xv = buf[1:].view(n, dim)
+        xv.copy_(torch.from_numpy(x32))
+        assert xv.data_ptr() % 16 != 0
+        f = c.func_evaluatef(fid, xv).cpu().numpy()
+        x32w = x32.astype(np.float64)
+        check32(orc, fid, p, x32w, f, p(x32w), "unaligned")
+
+
 def test_outputs_beyond_n_untouched_and_zero_rows(env):
     c, orc, torch, use = env
     use(30)
