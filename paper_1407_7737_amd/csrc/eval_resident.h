@@ -705,7 +705,38 @@ __device__ __forceinline__ void resident_eval(const DevProb &pb, const typename 
       }
     }
 
-    if constexpr (KT_::pairwise) {
+    if constexpr (KT_::pairwise && P != PATH_F64) {
+      // a lane's four positions of an m-tile are consecutive (16 m + 4 q + e): their successor
+      // indices (one 8-byte read), own z (one 16-byte read) and the four successors' z are all
+      // requested before the formula work, one LDS round trip per m-tile instead of one per
+      // element
+      typedef short i16x4 __attribute__((ext_vector_type(4)));
+      wave_sync();
+      for (int m = 0; m < MT; ++m) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const T *zr = Y + (b * kRowsPerBlock + r) * S;
+          const int p0 = 16 * m + 4 * q;
+          const i16x4 s4 = *reinterpret_cast<const i16x4 *>(s_succ + p0);
+          const f32x4 own = *reinterpret_cast<const f32x4 *>(zr + p0);
+          const int sp[4] = {s4[0], s4[1], s4[2], s4[3]};
+          T nx[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) nx[e] = zr[sp[e] < 0 ? p0 + e : sp[e]];
+          // keep the reads together ahead of the arithmetic
+          __builtin_amdgcn_sched_barrier(0);
+          T v = T(0);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            T w[3] = {T(0), T(0), T(0)};
+            phi<KIND, T>(w, a[b].p, own[e], nx[e], T(0), prm);
+            v += sp[e] < 0 ? T(0) : w[0];
+          }
+          acc_add<KIND, T>(a[b], 0, v);
+        }
+      }
+    } else if constexpr (KT_::pairwise) {
+      // FP64 rotated layout: a lane's positions 16 m + 4 e + q are not consecutive
       wave_sync();
       for (int m = 0; m < MT; ++m) {
 #pragma unroll
