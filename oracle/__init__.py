@@ -1,6 +1,6 @@
 """CPU FP64 oracle for the cuROB test functions (arXiv 1407.7737) -- test infrastructure.
 
-This package is the correctness judge for the GPU library.  It is a ctypes binding to
+This package is the correctness reference for the GPU library.  It is a ctypes binding to
 ``curob_oracle.c``: plain FP64 loops that evaluate each definition of the paper literally
 (shift, dense rotation, formula, bias).  It shares no code with ``paper_1407_7737_amd`` and is
 only imported by ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of

@@ -2,7 +2,7 @@
  * curob_oracle.c -- plain, slow, FP64 CPU oracle for the cuROB test-function suite
  * (Ding & Tan, "A CUDA-Based Real Parameter Optimization Benchmark", arXiv 1407.7737).
  *
- * TEST INFRASTRUCTURE ONLY.  This file is the correctness judge for the GPU library in
+ * TEST INFRASTRUCTURE ONLY.  This file is the correctness reference for the GPU library in
  * paper_1407_7737_amd/.  It shares no code, header, table or helper with that library and
  * must never be linked into it.  Only tests/, __graft_entry__.smoke() and the cpu_baseline
  * leg of bench.py load it.
