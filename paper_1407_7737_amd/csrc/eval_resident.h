@@ -578,6 +578,8 @@ __device__ __forceinline__ void resident_eval(const DevProb &pb, const typename 
       // the row group's loads, issued one iteration earlier, have landed in the slice
       __builtin_amdgcn_s_waitcnt(kWaitVmem);
       wave_sync();
+      // the gather leads to the group's first products: it runs at raised priority too
+      __builtin_amdgcn_s_setprio(1);
     } else {
       wave_sync();
       xt.template stage<is_split(P)>(nload, D, S, Y, s_oh, lane);
@@ -598,6 +600,7 @@ __device__ __forceinline__ void resident_eval(const DevProb &pb, const typename 
       // the gather's reads of the slice are complete before the next group's rows overwrite it
       __builtin_amdgcn_s_waitcnt(kWaitLds);
       wave_sync();
+      __builtin_amdgcn_s_setprio(0);
       if (gn < gend) load_rows_direct(rows_rsrc(x, gn * ROWS, n, D), D, S, reinterpret_cast<float *>(Y), wide, lane);
       if (q == 0 && prow < n) out[prow] = pend;
     }
@@ -614,10 +617,14 @@ __device__ __forceinline__ void resident_eval(const DevProb &pb, const typename 
       if constexpr (FIX) {
         const int code = __builtin_amdgcn_readfirstlane(mv.w);
         const int t0 = __builtin_amdgcn_readfirstlane(mv.z);
+        // the wave issues its products at raised priority, so the matrix core gets them ahead
+        // of other waves' formula work on the SIMD
+        __builtin_amdgcn_s_setprio(1);
         dispatch_krange(code, [&](auto c) {
           constexpr int C = decltype(c)::value;
           mtile_fixed<P, C / 4, C % 4 + 1>(acc, t0, bf, s_q, lane);
         });
+        __builtin_amdgcn_s_setprio(0);
       }
     };
 
