@@ -85,6 +85,13 @@ def lib():
             "orc_splitmix64_from_state": (u64, [u64, i64]),
             "orc_orthonormalise": (None, [i32, dp]),
             "orc_num_threads_available": (i32, []),
+            "orc_table_xform": (i32, [i32, dp, dp, ip]),
+            "orc_table_hybrid": (i32, [i32, dp, ip]),
+            "orc_table_composition": (i32, [i32, dp, dp, ip]),
+            "orc_problem_basic_params": (i32, [P, ip, dp, dp, ip]),
+            "orc_problem_group_bases": (i32, [P, ip]),
+            "orc_problem_blend_params": (i32, [P, dp, dp, dp]),
+            "orc_problem_component": (P, [P, i32]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -103,20 +110,54 @@ def _ip(a):
 
 
 class Problem:
-    """One oracle problem (basic, hybrid or composition)."""
+    """One oracle problem (basic, hybrid or composition).  A component of a composition is a
+    borrowed view: it keeps its composition alive and never frees the handle itself."""
 
-    def __init__(self, handle):
+    def __init__(self, handle, owner=None):
         if not handle:
             raise ValueError("oracle rejected the problem definition")
         self._h = handle
+        self._owner = owner
         self.dim = lib().orc_problem_dim(handle)
         self.kind = lib().orc_problem_kind(handle)
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h and _lib is not None:
+        if h and _lib is not None and getattr(self, "_owner", None) is None:
             _lib.orc_problem_free(h)
-            self._h = None
+        self._h = None
+
+    def ncomp(self) -> int:
+        """Components (composition), groups (hybrid) or 1 (basic)."""
+        return int(lib().orc_problem_ncomp(self._h))
+
+    def component(self, i: int) -> "Problem":
+        """Component i of a composition (a basic or hybrid problem)."""
+        h = lib().orc_problem_component(self._h, int(i))
+        if not h:
+            raise IndexError(i)
+        return Problem(h, owner=self)
+
+    def basic_params(self):
+        """(formula id, s, c, rotated) a basic problem was built with."""
+        b, r = ctypes.c_int(), ctypes.c_int()
+        s, c = ctypes.c_double(), ctypes.c_double()
+        assert lib().orc_problem_basic_params(self._h, ctypes.byref(b), ctypes.byref(s), ctypes.byref(c),
+                                              ctypes.byref(r)) == 0
+        return b.value, s.value, c.value, bool(r.value)
+
+    def group_bases(self) -> list:
+        out = np.zeros(16, dtype=np.int32)
+        n = lib().orc_problem_group_bases(self._h, _ip(out))
+        assert n > 0
+        return [int(v) for v in out[:n]]
+
+    def blend_params(self):
+        """(sigma, lambda, bias) arrays of a composition."""
+        a = [np.zeros(16) for _ in range(3)]
+        n = lib().orc_problem_blend_params(self._h, *[_dp(v) for v in a])
+        assert n > 0
+        return tuple(v[:n].copy() for v in a)
 
     def __call__(self, x, threads: int = 1) -> np.ndarray:
         x = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
@@ -183,6 +224,31 @@ def composition(pid: int, dim: int, seed: int, bases, sigma, lam, bias) -> Probl
     lm = np.ascontiguousarray(lam, dtype=np.float64)
     bi = np.ascontiguousarray(bias, dtype=np.float64)
     return Problem(lib().orc_problem_composition(pid, dim, seed, len(b), _ip(b), _dp(s), _dp(lm), _dp(bi)))
+
+
+def table_xform(fid: int):
+    """(s, c, rotated) as transcribed in the oracle's table for Tab. 1 function fid."""
+    s, c, r = ctypes.c_double(), ctypes.c_double(), ctypes.c_int()
+    assert lib().orc_table_xform(int(fid), ctypes.byref(s), ctypes.byref(c), ctypes.byref(r)) == 0
+    return s.value, c.value, bool(r.value)
+
+
+def table_hybrid(fid: int):
+    """(p, G ids) as transcribed in the oracle's table for hybrid fid (23..28)."""
+    p = np.zeros(16)
+    g = np.zeros(16, dtype=np.int32)
+    n = lib().orc_table_hybrid(int(fid), _dp(p), _ip(g))
+    assert n > 0
+    return [float(v) for v in p[:n]], [int(v) for v in g[:n]]
+
+
+def table_composition(fid: int):
+    """(sigma, lambda, G ids) as transcribed in the oracle's table for composition fid (29..36)."""
+    s, lm = np.zeros(16), np.zeros(16)
+    g = np.zeros(16, dtype=np.int32)
+    n = lib().orc_table_composition(int(fid), _dp(s), _dp(lm), _ip(g))
+    assert n > 0
+    return [float(v) for v in s[:n]], [float(v) for v in lm[:n]], [int(v) for v in g[:n]]
 
 
 def g(fid: int, z) -> float:

@@ -21,6 +21,9 @@
  * Parity status: every formula is pinned by tests/test_oracle_*.py against closed forms,
  * invariants, special cases and D=2 brute force, except where noted "parity unpinned" below
  * (agreement with the original cuROB binaries and data, which the paper does not provide).
+ * The transcribed constants -- each function's scale, offset and rotation flag (Secs. 3-4),
+ * the hybrid tables (Sec. 5) and the composition tables (Sec. 6) -- are pinned against
+ * fixtures of the printed values, element by element and through the values they produce.
  */
 #include <math.h>
 #include <stdint.h>
@@ -829,4 +832,75 @@ int orc_num_threads_available(void) {
 #else
   return 1;
 #endif
+}
+
+/* ------------------------------------------------------------------------------------------
+ * The transcribed parameter tables and the parameters of constructed problems, so that tests
+ * can compare both with the values the paper prints (Secs. 3-6).
+ * ---------------------------------------------------------------------------------------- */
+
+/* scale, offset and rotation flag of Tab. 1 function fid (0..22), Secs. 3-4 */
+int orc_table_xform(int fid, double *s, double *c, int *rotated) {
+  if (fid < 0 || fid > 22) return -1;
+  *s = ORC_XF[fid].s;
+  *c = ORC_XF[fid].c;
+  *rotated = ORC_XF[fid].rotated;
+  return 0;
+}
+
+/* Secs. 5.1-5.6: proportions p and component ids G of hybrid fid (23..28); returns N */
+int orc_table_hybrid(int fid, double *p, int *g) {
+  if (fid < 23 || fid > 28) return -1;
+  int h = fid - 23;
+  for (int i = 0; i < ORC_HY_N[h]; ++i) {
+    p[i] = ORC_HY_P[h][i];
+    g[i] = ORC_HY_G[h][i];
+  }
+  return ORC_HY_N[h];
+}
+
+/* Secs. 6.1-6.8: sigma, lambda and component ids of composition fid (29..36); returns N */
+int orc_table_composition(int fid, double *sigma, double *lambda, int *g) {
+  if (fid < 29 || fid > 36) return -1;
+  int c = fid - 29;
+  for (int i = 0; i < ORC_CO_N[c]; ++i) {
+    sigma[i] = ORC_CO_SIG[c][i];
+    lambda[i] = ORC_CO_LAM[c][i];
+    g[i] = ORC_CO_G[c][i];
+  }
+  return ORC_CO_N[c];
+}
+
+/* formula id, scale, offset and rotation flag a basic problem was built with */
+int orc_problem_basic_params(const orc_problem *p, int *base, double *s, double *c, int *rotated) {
+  if (!p || p->kind != ORC_BASIC) return -1;
+  *base = p->base;
+  *s = p->s;
+  *c = p->c;
+  *rotated = p->R != NULL;
+  return 0;
+}
+
+/* formula ids of the groups of a hybrid problem; returns the group count */
+int orc_problem_group_bases(const orc_problem *p, int *bases) {
+  if (!p || p->kind != ORC_HYBRID) return -1;
+  for (int g = 0; g < p->ngroups; ++g) bases[g] = p->gbase[g];
+  return p->ngroups;
+}
+
+/* sigma_i, lambda_i and bias_i a composition was built with; returns the component count */
+int orc_problem_blend_params(const orc_problem *p, double *sigma, double *lambda, double *bias) {
+  if (!p || p->kind != ORC_COMPOSITION) return -1;
+  for (int i = 0; i < p->ncomp; ++i) {
+    sigma[i] = p->sigma[i];
+    lambda[i] = p->lambda[i];
+    bias[i] = p->cbias[i];
+  }
+  return p->ncomp;
+}
+
+/* component i of a composition (owned by the composition, valid while it lives) */
+const orc_problem *orc_problem_component(const orc_problem *p, int i) {
+  if (!p || p->kind != ORC_COMPOSITION || i < 0 || i >= p->ncomp) return NULL;
+  return p->comp[i];
 }

@@ -6,8 +6,7 @@ At the optimum o^i of component i the distance d_i is zero, so the weights are o
 own optimum, except that components built on the modified Schwefel function keep the rounding
 of the printed constant 418.9829 (about 1.27e-5 per variable); with the printed lambda_i that
 leaves less than 10 x n x 1.3e-5.  The component count and every bias_i are thereby pinned to the
-paper; sigma_i and lambda_i are transcribed for reference (the weights are pinned by the closed
-forms of the composition tests)."""
+paper; sigma_i, lambda_i and the component ids are pinned in test_oracle_paper_tables.py."""
 import os
 
 import numpy as np
@@ -23,7 +22,7 @@ def paper_compositions():
         line = line.strip()
         if not line or line.startswith("#"):
             continue
-        fid, n, sig, lam, bias = line.split()
+        fid, n, sig, lam, bias, _g = line.split()
         rows.append((int(fid), int(n), [float(v) for v in sig.split(",")], [float(v) for v in lam.split(",")],
                      [float(v) for v in bias.split(",")]))
     return rows
