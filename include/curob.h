@@ -20,7 +20,14 @@
  *  - Ownership: the caller owns x and out; the library owns all problem data it generates,
  *    and dispose() frees it.  One library context per process; calls are not thread-safe.
  *  - Sizes: 0 <= n <= max_concurrency (the capacity fixed at initialize, Sec. 1.3); n = 0 is
- *    a no-op.  A null pointer with n > 0 is CUROB_E_ARG.
+ *    a no-op.  A null pointer with n > 0 is CUROB_E_ARG.  x must hold n rows of exactly the
+ *    `dim` given to initialize (curob_get_dim reports it); the library cannot check a raw
+ *    pointer's extent.
+ *  - Streams: hybrids, compositions and basic functions above 128 dimensions work through one
+ *    library-owned scratch buffer.  A call of that kind issued on another stream than the
+ *    previous one waits (on the device) for that previous call to finish; calls on one stream
+ *    are ordered by the stream.  Under stream capture no such wait is recorded: the capturing
+ *    caller keeps scratch-using calls on one stream.
  */
 #ifndef CUROB_H
 #define CUROB_H
@@ -104,7 +111,9 @@ int curob_define_basic(int id, int base, double scale, double offset, int rotate
 /* Hybrid function (Sec. 5, Eq. (hybrid)): y = x - o is permuted by a random S and cut into
  * ngroups consecutive groups of sizes n_i = ceil(p_i dim) (i < ngroups) and the remainder
  * (Eq. (numbers)); group i contributes g_{base_i}(R_i (s_i z^i) + c_i) at dimension n_i, with
- * its own dense random rotation R_i.  Every n_i must be >= 2; 1 <= ngroups <= 8. */
+ * its own dense random rotation R_i.  1 <= ngroups <= 8.  Every n_i must be >= 1, and >= 2 for
+ * the formulas that divide by n - 1 (elliptic 2, different powers 5, Schaffer F7 12); other
+ * sizes are CUROB_E_ARG. */
 int curob_define_hybrid(int id, int ngroups, const int *bases, const double *p);
 
 /* Composition function (Sec. 6, Eqs. (composition) and (weight)): ncomp (1..8) basic
@@ -125,6 +134,41 @@ int curob_get_problem(int fid, double *o, double *R);
 /* Host-only generator entry point (no device needed): the same o and R that initialize(dim,
  * ..., seed) produces for basic function `fid` (0..22). */
 int curob_generate_basic(int fid, int dim, unsigned long long seed, double *o, double *R);
+
+/* The dimension and capacity given to initialize.  CUROB_E_STATE before initialize. */
+int curob_get_dim(int *dim, int *max_concurrency);
+
+/* ---- problem structure export (for checks against an independent implementation) ---------
+ * A problem is described part by part: comp < 0 names the problem itself, comp = 0..N-1 a
+ * component of a composition (CUROB_E_ARG for other problems or out of range).
+ *
+ * curob_get_info: *type = 0 basic, 1 hybrid, 2 composition; *count = rotation blocks (basic:
+ *   the up to three variable groups of Sec. 1.2, 0 when unrotated; hybrid: its N groups, Sec. 5)
+ *   or components (composition, Sec. 6); *nseg = formula segments (basic 1, hybrid N, composition
+ *   0).  Any output pointer may be NULL.
+ * curob_get_structure: for a basic or hybrid part: o (dim doubles, the shift, original variable
+ *   order); perm (dim ints: packed position -> original variable, 0-based; the permutation S of
+ *   Sec. 5 Eq. (hybrid) for hybrids, the group order of Sec. 1.2 for basic functions); sizes
+ *   (count ints, block sizes n_k in packed order); blocks (sum n_k^2 doubles: each n_k x n_k
+ *   orthonormal block row-major, one after another, so z_a = sum_b Q[a][b] (s y_perm[off+b]) + c
+ *   within a block); bases, scale, offset (nseg entries: Tab. 1 formula id, s and c of each
+ *   segment).  Any pointer may be NULL; non-NULL ones must hold the sizes above.  A composition
+ *   itself (comp < 0) is CUROB_E_ARG: name a component.
+ * curob_get_composition: sigma_i, lambda_i and bias_i of a composition (count values each,
+ *   Sec. 6 Eq. (composition)); CUROB_E_ARG for other problems.
+ * These read the problem registered under fid in the initialised library (CUROB_E_STATE before
+ * initialize, CUROB_E_FID for an unknown id).  The curob_generate_* forms generate Tab. 1
+ * problem fid (0..36) for (dim, seed) on the host instead, exactly as initialize(dim, ..., seed)
+ * would, with no device and no library state (CUROB_E_ARG for dim < 2 or a hybrid below 10). */
+int curob_get_info(int fid, int comp, int *type, int *count, int *nseg);
+int curob_get_structure(int fid, int comp, double *o, int *perm, int *sizes, double *blocks, int *bases,
+                        double *scale, double *offset);
+int curob_get_composition(int fid, double *sigma, double *lambda, double *bias);
+int curob_generate_info(int fid, int dim, unsigned long long seed, int comp, int *type, int *count, int *nseg);
+int curob_generate_structure(int fid, int dim, unsigned long long seed, int comp, double *o, int *perm, int *sizes,
+                             double *blocks, int *bases, double *scale, double *offset);
+int curob_generate_composition(int fid, int dim, unsigned long long seed, double *sigma, double *lambda,
+                               double *bias);
 
 /* ---- batched populations (one persistent launch, replayed as a HIP graph) --------------- */
 

@@ -29,8 +29,13 @@ HYBRID1, COMPOSITION1 = 23, 29
 __all__ = [
     "initialize", "dispose", "func_evaluate", "func_evaluatef", "h_func_evaluate", "h_func_evaluatef",
     "set_stream", "set_mode", "define_basic", "define_hybrid", "define_composition", "get_problem",
-    "generate_basic", "last_error", "CurobError", "Batch",
+    "generate_basic", "get_dim", "get_structure", "get_composition", "generate_structure",
+    "generate_composition", "last_error", "CurobError", "Batch",
 ]
+
+# dimension given to initialize, for the shape checks of the device calls (None: not initialised
+# through this binding; the library is then asked)
+_dim = None
 
 
 def _ptr(t):
@@ -47,11 +52,26 @@ def _torch_stream():
 
 
 def initialize(dim: int, max_concurrency: int, seed: int = 0) -> None:
+    global _dim
     check(lib.initialize(int(dim), int(max_concurrency), int(seed)))
+    _dim = int(dim)
 
 
 def dispose() -> None:
+    global _dim
+    _dim = None
     check(lib.dispose())
+
+
+def get_dim() -> tuple:
+    """(dim, max_concurrency) given to initialize."""
+    d, m = ctypes.c_int(), ctypes.c_int()
+    check(lib.curob_get_dim(ctypes.byref(d), ctypes.byref(m)))
+    return d.value, m.value
+
+
+def _current_dim() -> int:
+    return _dim if _dim is not None else get_dim()[0]
 
 
 def set_stream(stream=None) -> None:
@@ -74,6 +94,9 @@ def _eval_device(fn, fid, x, out, dtype_name):
     want = torch.float64 if dtype_name == "f64" else torch.float32
     if not (x.is_cuda and x.dtype == want and x.is_contiguous() and x.dim() == 2):
         raise ValueError(f"x must be a contiguous 2-D {want} CUDA tensor")
+    dim = _current_dim()
+    if x.shape[1] != dim:
+        raise ValueError(f"x has rows of {x.shape[1]} elements, the library was initialised with dim {dim}")
     n = x.shape[0]
     if out is None:
         out = torch.empty(n, dtype=want, device=x.device)
@@ -107,6 +130,9 @@ def _eval_host(fn, fid, x, dt):
     x = np.ascontiguousarray(np.asarray(x, dtype=dt))
     if x.ndim == 1:
         x = x[None, :]
+    dim = _current_dim()
+    if x.ndim != 2 or x.shape[1] != dim:
+        raise ValueError(f"x must have rows of {dim} elements (got shape {x.shape})")
     out = np.empty(x.shape[0], dtype=dt)
     check(fn(int(fid), x.ctypes.data, int(x.shape[0]), out.ctypes.data))
     return out
@@ -140,7 +166,13 @@ def define_composition(pid: int, bases, sigma, lam, bias) -> None:
                                        *[a.ctypes.data_as(dp) for a in arrs]))
 
 
-def get_problem(fid: int, dim: int):
+def get_problem(fid: int, dim: int | None = None):
+    """Shift o and dense rotation R of a basic problem of the initialised library.  `dim`, if
+    given, must equal the initialised dimension (the buffers are sized from the library's)."""
+    d = _current_dim()
+    if dim is not None and int(dim) != d:
+        raise ValueError(f"the library was initialised with dim {d}, not {dim}")
+    dim = d
     o = np.empty(dim)
     R = np.empty((dim, dim))
     dp = ctypes.POINTER(ctypes.c_double)
@@ -155,6 +187,67 @@ def generate_basic(fid: int, dim: int, seed: int):
     dp = ctypes.POINTER(ctypes.c_double)
     check(lib.curob_generate_basic(int(fid), int(dim), int(seed), o.ctypes.data_as(dp), R.ctypes.data_as(dp)))
     return o, R
+
+
+def _structure(info_fn, struct_fn, lead, comp):
+    """Unpacks the curob_*_info / curob_*_structure pair (see include/curob.h)."""
+    t, cnt, ns = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    check(info_fn(*lead, int(comp), ctypes.byref(t), ctypes.byref(cnt), ctypes.byref(ns)))
+    res = {"type": ("basic", "hybrid", "composition")[t.value], "count": cnt.value}
+    if t.value == 2 and comp < 0:
+        return res
+    # sizes first (blocks need their total)
+    sizes = np.zeros(max(cnt.value, 1), dtype=np.int32)
+    dp, ip = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
+    check(struct_fn(*lead, int(comp), None, None, sizes.ctypes.data_as(ip), None, None, None, None))
+    sizes = sizes[:cnt.value]
+    dim = lead[-2] if len(lead) == 3 else _current_dim()
+    o = np.empty(dim)
+    perm = np.empty(dim, dtype=np.int32)
+    blocks = np.empty(max(int(np.sum(sizes.astype(np.int64) ** 2)), 1))
+    bases = np.empty(max(ns.value, 1), dtype=np.int32)
+    scale, offset = np.empty(max(ns.value, 1)), np.empty(max(ns.value, 1))
+    check(struct_fn(*lead, int(comp), o.ctypes.data_as(dp), perm.ctypes.data_as(ip), sizes.ctypes.data_as(ip),
+                    blocks.ctypes.data_as(dp), bases.ctypes.data_as(ip), scale.ctypes.data_as(dp),
+                    offset.ctypes.data_as(dp)))
+    mats, off = [], 0
+    for n in sizes:
+        mats.append(blocks[off:off + n * n].reshape(n, n).copy())
+        off += n * n
+    res.update(o=o, perm=perm, sizes=sizes, blocks=mats, bases=bases[:ns.value].copy(),
+               scale=scale[:ns.value].copy(), offset=offset[:ns.value].copy())
+    return res
+
+
+def _blend(fn, lead):
+    sig, lam, bias = np.zeros(16), np.zeros(16), np.zeros(16)
+    dp = ctypes.POINTER(ctypes.c_double)
+    check(fn(*lead, sig.ctypes.data_as(dp), lam.ctypes.data_as(dp), bias.ctypes.data_as(dp)))
+    return sig, lam, bias
+
+
+def get_structure(fid: int, comp: int = -1) -> dict:
+    """Structure of problem fid (or of component comp of a composition) in the initialised
+    library: type, count and, for basic and hybrid parts, o, perm (S), block sizes, blocks,
+    and per formula segment its Tab. 1 id, scale and offset (curob_get_structure)."""
+    return _structure(lib.curob_get_info, lib.curob_get_structure, (int(fid),), comp)
+
+
+def generate_structure(fid: int, dim: int, seed: int, comp: int = -1) -> dict:
+    """Host-only form of get_structure for Tab. 1 id fid at (dim, seed); no device needed."""
+    return _structure(lib.curob_generate_info, lib.curob_generate_structure, (int(fid), int(dim), int(seed)), comp)
+
+
+def get_composition(fid: int):
+    """(sigma, lambda, bias) of a composition of the initialised library."""
+    n = get_structure(fid)["count"]
+    return tuple(a[:n] for a in _blend(lib.curob_get_composition, (int(fid),)))
+
+
+def generate_composition(fid: int, dim: int, seed: int):
+    """Host-only (sigma, lambda, bias) of Tab. 1 composition fid at (dim, seed)."""
+    n = generate_structure(fid, dim, seed)["count"]
+    return tuple(a[:n] for a in _blend(lib.curob_generate_composition, (int(fid), int(dim), int(seed))))
 
 
 def probe_read_gbs(x, reps: int = 10) -> float:

@@ -31,7 +31,8 @@ EXPORTED = [
     "curob_define_composition", "curob_last_error", "curob_get_problem", "curob_generate_basic",
     "curob_batch_create", "curob_batch_bind", "curob_batch_run", "curob_batch_run_direct",
     "curob_batch_configure", "curob_batch_shape", "curob_batch_tune", "curob_batch_destroy",
-    "curob_probe_read", "curob_probe_mfma_bf16",
+    "curob_probe_read", "curob_probe_mfma_bf16", "curob_get_dim", "curob_get_info", "curob_get_structure",
+    "curob_get_composition", "curob_generate_info", "curob_generate_structure", "curob_generate_composition",
 ]
 BATCH_KEY_BASE = 2048  # population i of a batch keys its random data like custom id 2048 + i
 
@@ -73,6 +74,13 @@ def _load():
         "curob_batch_destroy": (i32, [vp]),
         "curob_probe_read": (i32, [vp, u64, i32, ctypes.POINTER(ctypes.c_double)]),
         "curob_probe_mfma_bf16": (i32, [i32, ctypes.POINTER(ctypes.c_double)]),
+        "curob_get_dim": (i32, [ip, ip]),
+        "curob_get_info": (i32, [i32, i32, ip, ip, ip]),
+        "curob_get_structure": (i32, [i32, i32, dp, ip, ip, dp, ip, dp, dp]),
+        "curob_get_composition": (i32, [i32, dp, dp, dp]),
+        "curob_generate_info": (i32, [i32, i32, u64, i32, ip, ip, ip]),
+        "curob_generate_structure": (i32, [i32, i32, u64, i32, dp, ip, ip, dp, ip, dp, dp]),
+        "curob_generate_composition": (i32, [i32, i32, u64, dp, dp, dp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)

@@ -43,6 +43,11 @@ struct Context {
   CompositeScratch scratch;   // tiled partial sums, pairwise z, composition components
   void *stage_x = nullptr;    // maxc * dim doubles, for the h_ wrappers
   void *stage_out = nullptr;  // maxc doubles
+  // The scratch is shared by every tiled and composition call: a call on another stream than
+  // the previous scratch user first waits for this event, recorded after that call.
+  hipEvent_t scratch_done = nullptr;
+  hipStream_t scratch_stream = nullptr;
+  bool scratch_used = false;
 };
 
 Context g_ctx;
@@ -67,6 +72,7 @@ void free_context() {
   g_ctx.scratch.release();
   if (g_ctx.stage_x) (void)hipFree(g_ctx.stage_x);
   if (g_ctx.stage_out) (void)hipFree(g_ctx.stage_out);
+  if (g_ctx.scratch_done) (void)hipEventDestroy(g_ctx.scratch_done);
   g_ctx = Context{};
 }
 
@@ -151,7 +157,22 @@ int evaluate(int path, int fid, const void *x, int n, void *out) {
     he = launch_resident(path, pb, x, out, n, resident_shape(path, pb, n, g_ctx.num_cu), g_ctx.stream);
   } else if (e->comp.ready) {
     const bool split_auto = g_ctx.mode == CUROB_MODE_SPLIT && path != PATH_F64;
+    // order this call after the previous user of the shared scratch when that ran on another
+    // stream; under stream capture the caller orders its captured work itself
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    he = hipStreamIsCapturing(g_ctx.stream, &cap);
+    if (he != hipSuccess) return hip_fail(he, "querying stream capture");
+    const bool track = cap == hipStreamCaptureStatusNone;
+    if (track && g_ctx.scratch_used && g_ctx.scratch_stream != g_ctx.stream) {
+      he = hipStreamWaitEvent(g_ctx.stream, g_ctx.scratch_done, 0);
+      if (he != hipSuccess) return hip_fail(he, "ordering scratch use across streams");
+    }
     he = launch_composite(path, split_auto, e->comp, x, out, n, g_ctx.num_cu, g_ctx.scratch, g_ctx.stream);
+    if (he == hipSuccess && track) {
+      he = hipEventRecord(g_ctx.scratch_done, g_ctx.stream);
+      g_ctx.scratch_stream = g_ctx.stream;
+      g_ctx.scratch_used = true;
+    }
   } else {
     return fail(CUROB_E_HIP, "function id %d has no device tables", fid);
   }
@@ -173,6 +194,84 @@ int h_evaluate(int path, int fid, const T *hx, int n, T *hout) {
   if (he != hipSuccess) return hip_fail(he, "copying results to the host");
   he = hipStreamSynchronize(g_ctx.stream);
   if (he != hipSuccess) return hip_fail(he, "waiting for the evaluation");
+  return CUROB_OK;
+}
+
+// The part of a problem an export call describes: the problem itself (comp < 0) or component
+// comp of a composition.
+int select_part(const Problem &top, int comp, const Problem **part) {
+  if (comp < 0) {
+    *part = &top;
+    return CUROB_OK;
+  }
+  if (top.type != Problem::COMPOSITION) return fail(CUROB_E_ARG, "only compositions have components");
+  if (comp >= static_cast<int>(top.comps.size()))
+    return fail(CUROB_E_ARG, "component %d out of range (%d components)", comp, static_cast<int>(top.comps.size()));
+  *part = &top.comps[static_cast<size_t>(comp)];
+  return CUROB_OK;
+}
+
+int export_info(const Problem &top, int comp, int *type, int *count, int *nseg) {
+  const Problem *p = nullptr;
+  int rc = select_part(top, comp, &p);
+  if (rc != CUROB_OK) return rc;
+  if (type) *type = p->type;
+  if (count) *count = p->type == Problem::COMPOSITION ? static_cast<int>(p->comps.size()) : static_cast<int>(p->Q.size());
+  if (nseg) *nseg = static_cast<int>(p->segs.size());
+  return CUROB_OK;
+}
+
+int export_structure(const Problem &top, int comp, double *o, int *perm, int *sizes, double *blocks, int *bases,
+                     double *scale, double *offset) {
+  const Problem *p = nullptr;
+  int rc = select_part(top, comp, &p);
+  if (rc != CUROB_OK) return rc;
+  if (p->type == Problem::COMPOSITION)
+    return fail(CUROB_E_ARG, "a composition has no single structure: name a component");
+  if (o) std::memcpy(o, p->o.data(), sizeof(double) * p->o.size());
+  if (perm) std::memcpy(perm, p->orig.data(), sizeof(int) * p->orig.size());
+  size_t off = 0;
+  for (size_t k = 0; k < p->Q.size(); ++k) {
+    if (sizes) sizes[k] = p->blk_n[k];
+    if (blocks) std::memcpy(blocks + off, p->Q[k].data(), sizeof(double) * p->Q[k].size());
+    off += p->Q[k].size();
+  }
+  for (size_t i = 0; i < p->segs.size(); ++i) {
+    if (bases) bases[i] = p->segs[i].base;
+    if (scale) scale[i] = p->segs[i].s;
+    if (offset) offset[i] = p->segs[i].c;
+  }
+  return CUROB_OK;
+}
+
+int export_composition(const Problem &p, double *sigma, double *lambda, double *bias) {
+  if (p.type != Problem::COMPOSITION) return fail(CUROB_E_ARG, "not a composition");
+  for (size_t i = 0; i < p.comps.size(); ++i) {
+    if (sigma) sigma[i] = p.sigma[i];
+    if (lambda) lambda[i] = p.lambda[i];
+    if (bias) bias[i] = p.cbias[i];
+  }
+  return CUROB_OK;
+}
+
+int find_entry(int fid, const Problem **p) {
+  int rc = check_ready();
+  if (rc != CUROB_OK) return rc;
+  auto it = g_ctx.entries.find(fid);
+  if (it == g_ctx.entries.end()) return fail(CUROB_E_FID, "function id %d is not defined", fid);
+  *p = &it->second->host;
+  return CUROB_OK;
+}
+
+// A Tab. 1 problem generated on the host only (no device, no context).
+int generate_tab1(int fid, int dim, unsigned long long seed, Problem &p) {
+  if (fid < 0 || fid > 36) return fail(CUROB_E_FID, "fid must be in 0..36");
+  if (dim < 2) return fail(CUROB_E_ARG, "dim must be >= 2");
+  try {
+    p = make_tab1(fid, dim, seed);
+  } catch (const std::exception &ex) {
+    return fail(CUROB_E_ARG, "%s", ex.what());
+  }
   return CUROB_OK;
 }
 
@@ -218,6 +317,11 @@ int initialize(int dim, int max_concurrency, unsigned long long seed) {
   } catch (const std::exception &ex) {
     free_context();
     return fail(CUROB_E_ARG, "%s", ex.what());
+  }
+  he = hipEventCreateWithFlags(&g_ctx.scratch_done, hipEventDisableTiming);
+  if (he != hipSuccess) {
+    free_context();
+    return hip_fail(he, "creating the scratch event");
   }
   const size_t xb = static_cast<size_t>(max_concurrency) * dim * sizeof(double);
   he = hipMalloc(&g_ctx.stage_x, xb);
@@ -325,6 +429,53 @@ int curob_get_problem(int fid, double *o, double *R) {
     std::memcpy(R, d.data(), sizeof(double) * d.size());
   }
   return CUROB_OK;
+}
+
+int curob_get_dim(int *dim, int *max_concurrency) {
+  int rc = check_ready();
+  if (rc != CUROB_OK) return rc;
+  if (dim) *dim = g_ctx.dim;
+  if (max_concurrency) *max_concurrency = g_ctx.maxc;
+  return CUROB_OK;
+}
+
+int curob_get_info(int fid, int comp, int *type, int *count, int *nseg) {
+  const Problem *p = nullptr;
+  int rc = find_entry(fid, &p);
+  return rc != CUROB_OK ? rc : export_info(*p, comp, type, count, nseg);
+}
+
+int curob_get_structure(int fid, int comp, double *o, int *perm, int *sizes, double *blocks, int *bases,
+                        double *scale, double *offset) {
+  const Problem *p = nullptr;
+  int rc = find_entry(fid, &p);
+  return rc != CUROB_OK ? rc : export_structure(*p, comp, o, perm, sizes, blocks, bases, scale, offset);
+}
+
+int curob_get_composition(int fid, double *sigma, double *lambda, double *bias) {
+  const Problem *p = nullptr;
+  int rc = find_entry(fid, &p);
+  return rc != CUROB_OK ? rc : export_composition(*p, sigma, lambda, bias);
+}
+
+int curob_generate_info(int fid, int dim, unsigned long long seed, int comp, int *type, int *count, int *nseg) {
+  Problem p;
+  int rc = generate_tab1(fid, dim, seed, p);
+  return rc != CUROB_OK ? rc : export_info(p, comp, type, count, nseg);
+}
+
+int curob_generate_structure(int fid, int dim, unsigned long long seed, int comp, double *o, int *perm, int *sizes,
+                             double *blocks, int *bases, double *scale, double *offset) {
+  Problem p;
+  int rc = generate_tab1(fid, dim, seed, p);
+  return rc != CUROB_OK ? rc : export_structure(p, comp, o, perm, sizes, blocks, bases, scale, offset);
+}
+
+int curob_generate_composition(int fid, int dim, unsigned long long seed, double *sigma, double *lambda,
+                               double *bias) {
+  Problem p;
+  int rc = generate_tab1(fid, dim, seed, p);
+  return rc != CUROB_OK ? rc : export_composition(p, sigma, lambda, bias);
 }
 
 int curob_generate_basic(int fid, int dim, unsigned long long seed, double *o, double *R) {

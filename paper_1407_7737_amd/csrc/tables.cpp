@@ -188,7 +188,7 @@ bool build_host_tables(const Problem &p, int path, HostTables &ht, std::string &
   ht.goff.assign(pad16(KT * KW * 2) / 2, static_cast<uint16_t>(D * esz));
   for (int pp = 0; pp < D; ++pp) ht.goff[pp] = static_cast<uint16_t>(order[pp] * esz);
   // per packed position: c' = c - s (Q o_lo)_p, coefficient, formula successor.  Padding gets
-  // z = 0 and neutral coefficients.  Schwefel's g1 takes z + 420.9687..., folded into c' (its
+  // z = 0 (Weierstrass: -1/2) and neutral coefficients.  Schwefel's g1 takes z + 420.9687..., folded into c' (its
   // padding then gives w = 0, where g1 vanishes).
   ht.cz.assign(pad16(Mp * esz), 0);
   ht.coef.assign(pad16(Mp * esz), 0);
@@ -196,6 +196,9 @@ bool build_host_tables(const Problem &p, int path, HostTables &ht, std::string &
   for (int pp = 0; pp < Mp; ++pp) {
     if (pp >= D) {
       if (kind == K_POWERS) store(ht.coef, pp, 2.0);
+      // Weierstrass padding takes z = -1/2, so every cosine argument 2 pi 3^k (z + 1/2) is
+      // exactly 0 in any precision (3^k itself is not exact in FP32 beyond k = 15)
+      if (kind == K_WEIERSTRASS) store(ht.cz, pp, -0.5);
       continue;
     }
     const int i = order[pp];  // index the formula sees (original variable order)
@@ -284,7 +287,7 @@ bool build_host_tables(const Problem &p, int path, HostTables &ht, std::string &
   // what the padded positions (z = 0, or w = 0 for Schwefel) add to each sum
   const double npad = static_cast<double>(Mp - D);
   pb.padc[0] = pb.padc[1] = pb.padc[2] = 0.0;
-  if (kind == K_WEIERSTRASS) pb.padc[0] = -npad * (2.0 - 9.5367431640625e-07);  // sum_k a^k cos(pi 3^k)
+  if (kind == K_WEIERSTRASS) pb.padc[0] = npad * (2.0 - 9.5367431640625e-07);   // sum_k a^k cos(0)
   if (kind == K_ACKLEY) pb.padc[1] = npad;                                          // cos(0) = 1
   if (kind == K_HAPPYCAT) pb.padc[0] = -npad;                                       // 0^2 - 1
   if (kind == K_LUNACEK) {

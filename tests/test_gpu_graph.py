@@ -23,6 +23,15 @@ def say(*a):
     sys.stdout.flush()
 
 
+def schwefel_edge_rows(orc, p, x):
+    s, c, _ = orc.table_xform(16)
+    y = s * (x - p.shift()[None, :])
+    w = np.abs(y @ p.rotation().T + c + 420.9687462275036)
+    d = np.where(w >= 750.0, np.abs(w - 500.0 * np.round(w / 500.0)), np.inf)
+    delta = 64.0 * 2.0 ** -24 * (1.0 + np.linalg.norm(y, axis=1, keepdims=True))
+    return (d < delta).any(axis=1)
+
+
 @pytest.mark.parametrize("dim", [10, 32, 64, 96])
 def test_graph_replay_matches_eager(dim):
     import torch
@@ -47,10 +56,14 @@ def test_graph_replay_matches_eager(dim):
             p = oracle.basic(f, dim, SEED)
             ref = p(x64)
             assert np.max(np.abs(e64[f].cpu().numpy() - ref) / np.maximum(1, np.abs(ref))) <= TOL64
-            ref32 = p(x32.astype(np.float64))
+            x32w = x32.astype(np.float64)
+            ref32 = p(x32w)
             err = np.abs(e32[f].cpu().numpy() - ref32) / np.maximum(1, np.abs(ref32))
-            if f != 16:  # Schwefel rows at a jump are covered by the parity tests
-                assert err.max() <= TOL32, (dim, f, float(err.max()))
+            if f == 16:
+                # rotated Schwefel: only rows with a component of w = z + 420.97 within FP32
+                # rounding (64 ulp of |y|) of a g1 jump at |w| = 1000, 1500, ... are exempt
+                err = np.where(schwefel_edge_rows(oracle, p, x32w), 0.0, err)
+            assert err.max() <= TOL32, (dim, f, float(err.max()))
         # one graph with every call
         g = torch.cuda.CUDAGraph()
         s = torch.cuda.Stream()

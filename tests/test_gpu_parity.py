@@ -212,6 +212,36 @@ def test_host_wrappers_match_device_calls(env):
         assert np.array_equal(df, hf)
 
 
+def test_wrong_row_width_is_rejected(env):
+    c, orc, torch, use = env
+    use(30)
+    x = torch.zeros((4, 29), dtype=torch.float32, device="cuda")
+    with pytest.raises(ValueError):
+        c.func_evaluatef(0, x)
+    with pytest.raises(ValueError):
+        c.get_problem(0, 29)
+    assert c.get_dim() == (30, 1 << 18)
+
+
+def test_context_structure_equals_host_generator(env):
+    """curob_get_* on the initialised library describe the problems it evaluates; they equal
+    the host-only generator's output (itself checked against the oracle without a GPU)."""
+    c, orc, torch, use = env
+    use(30)
+    for fid, comps in ((11, [-1]), (25, [-1]), (31, [0, 1, 2]), (35, [0, 1, 2])):
+        for comp in comps:
+            a = c.get_structure(fid, comp)
+            b = c.generate_structure(fid, 30, SEED, comp)
+            assert a.keys() == b.keys()
+            for k in a:
+                if k == "blocks":
+                    assert all(np.array_equal(u, v) for u, v in zip(a[k], b[k]))
+                else:
+                    assert np.array_equal(np.asarray(a[k]), np.asarray(b[k])), (fid, comp, k)
+    for fid in (29, 33, 36):
+        assert all(np.array_equal(u, v) for u, v in zip(c.get_composition(fid), c.generate_composition(fid, 30, SEED)))
+
+
 def test_library_problem_equals_oracle_problem(env):
     c, orc, torch, use = env
     use(64)
@@ -255,7 +285,8 @@ def test_nondefault_stream(env):
 @pytest.mark.parametrize("fid", [0, 2, 9, 10, 11, 14, 16, 19])
 def test_full_size_d100_n2p18(env, fid):
     """The measured workload (D = 100, N = 2^18) in the launch configuration the bench uses
-    (default split mode), every row compared with the oracle."""
+    (default split mode), and the plain FP32 mode beside it, every row compared with the
+    oracle; the FP64 path on the same points."""
     c, orc, torch, use = env
     use(100)
     from paper_1407_7737_amd.inputs import population
@@ -267,8 +298,12 @@ def test_full_size_d100_n2p18(env, fid):
     ref = p(x64, threads=16)
     dx32 = torch.from_numpy(x32).cuda()
     fs = c.func_evaluatef(fid, dx32).cpu().numpy()
+    c.set_mode(c.MODE_FP32)
+    fp = c.func_evaluatef(fid, dx32).cpu().numpy()
+    c.set_mode(c.MODE_SPLIT)
     f64 = c.func_evaluate(fid, torch.from_numpy(x64).cuda()).cpu().numpy()
     e64 = rel_err(f64, ref)
     es = check32(orc, fid, p, x64, fs, ref, "split-full")
-    say(f"[full] fid={fid} split max {es:.3e}; fp64 max {e64.max():.3e}")
+    ep = check32(orc, fid, p, x64, fp, ref, "fp32-full")
+    say(f"[full] fid={fid} split max {es:.3e}; fp32 max {ep:.3e}; fp64 max {e64.max():.3e}")
     assert e64.max() <= TOL64
