@@ -90,6 +90,19 @@ int func_evaluate(int fid, const double *d_x, int n, double *d_out);
  * six-product split, all others the three-product split. */
 int func_evaluatef(int fid, const float *d_x, int n, float *d_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): func_evaluatef with no allocation of any kind.  Same
+ * arguments, arithmetic, results and errors as func_evaluatef, asynchronous on the library
+ * stream.  Problems whose kernels need scratch (hybrids, compositions, basic functions above
+ * 128 dimensions) take it from a static device array of CUROB_NOALLOC_SCRATCH_BYTES per device,
+ * held until the process ends, in passes of as many rows as fit (at most 65536); a problem
+ * whose 128-row pass does not fit is CUROB_E_CAPACITY.  Every call on a device shares that
+ * device's array: calls that overlap on one device (other streams or threads) race and must
+ * be serialised by the caller.  Nothing in the array needs clearing between calls: every
+ * kernel writes each scratch entry it reads within the same call. */
+#define CUROB_NOALLOC_SCRATCH_BYTES (32ull << 20)
+int func_evaluatef_noalloc(int fid, const float *d_x, int n, float *d_out);
+
 /* Host-pointer wrappers of the two calls above (Sec. 1.3): copy h_x to the device, evaluate,
  * copy the results to h_out and wait for them. */
 int h_func_evaluate(int fid, const double *h_x, int n, double *h_out);
@@ -169,6 +182,28 @@ int curob_generate_structure(int fid, int dim, unsigned long long seed, int comp
                              double *blocks, int *bases, double *scale, double *offset);
 int curob_generate_composition(int fid, int dim, unsigned long long seed, double *sigma, double *lambda,
                                double *bias);
+
+/* ---- an optimiser in the loop: differential evolution on the GPU ------------------------
+ * The paper's motivating use (Sec. 1; Sec. 2 evaluates 50 candidates per call): an optimiser
+ * running on the GPU calls the evaluation interface every generation.  curob_de_run enqueues
+ * `generations` generations of DE/rand/1/bin on the library stream, each: trial vectors from
+ * the population, their evaluation through func_evaluate (fp64 != 0) or func_evaluatef, and
+ * greedy selection (a trial replaces its target when its value is not larger), then the
+ * device generation counter *d_gen advances by one.  Nothing is allocated, copied or cleared,
+ * so the call can be captured in a HIP graph; replays continue from the counter.
+ * Trial of individual i in generation g: r1, r2, r3 distinct and != i, a forced position
+ * j_rand, and for each variable j: t_j = clamp(fma(F, x_r2j - x_r3j, x_r1j), -100, 100) if
+ * u_j < CR or j = j_rand, else x_ij (FP64 or FP32 arithmetic as the population).  Random draw k
+ * is SplitMix64's output for state seed + (k + 1) 0x9E3779B97F4A7C15 with k = (g np + i)(dim + 4)
+ * + slot; slots 0, 1, 2 pick r1, r2, r3 (each the v-th allowed index in increasing order,
+ * v = draw mod (number allowed)), slot 3 gives j_rand = draw mod dim, slot 4 + j gives
+ * u_j = (draw >> 11) 2^-53.
+ * Buffers (device, caller-owned, of the population's type): d_pop np x dim, d_fit np (the
+ * values of d_pop, e.g. from func_evaluate[f]), d_trial np x dim and d_ftrial np (work space),
+ * d_gen one unsigned 64-bit generation counter.  4 <= np <= max_concurrency, 0 < F <= 2,
+ * 0 <= CR <= 1; otherwise CUROB_E_ARG (CUROB_E_CAPACITY for np > max_concurrency). */
+int curob_de_run(int fid, int fp64, int np, double F, double CR, unsigned long long seed, void *d_pop, void *d_fit,
+                 void *d_trial, void *d_ftrial, unsigned long long *d_gen, int generations);
 
 /* ---- batched populations (one persistent launch, replayed as a HIP graph) --------------- */
 

@@ -92,6 +92,7 @@ def lib():
             "orc_problem_group_bases": (i32, [P, ip]),
             "orc_problem_blend_params": (i32, [P, dp, dp, dp]),
             "orc_problem_component": (P, [P, i32]),
+            "orc_de_run": (f64, [P, i32, f64, f64, u64, u64, i32, dp, dp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -190,6 +191,12 @@ class Problem:
             out.append(blocks[off:off + n * n].reshape(n, n).copy())
             off += n * n
         return perm, sizes, out
+
+    def de_run(self, pop, fit, F: float, CR: float, seed: int, gen0: int, generations: int) -> float:
+        """DE/rand/1/bin for `generations` generations from generation gen0, updating the (np, D)
+        array pop and the (np,) array fit in place; returns the closest selection margin."""
+        assert pop.dtype == np.float64 and pop.flags.c_contiguous and fit.dtype == np.float64
+        return float(lib().orc_de_run(self._h, pop.shape[0], F, CR, seed, gen0, generations, _dp(pop), _dp(fit)))
 
     def transform(self, x) -> np.ndarray:
         x = np.ascontiguousarray(np.asarray(x, dtype=np.float64))

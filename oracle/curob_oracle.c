@@ -904,3 +904,71 @@ const orc_problem *orc_problem_component(const orc_problem *p, int i) {
   if (!p || p->kind != ORC_COMPOSITION || i < 0 || i >= p->ncomp) return NULL;
   return p->comp[i];
 }
+
+/* ------------------------------------------------------------------------------------------
+ * Differential evolution (DE/rand/1/bin) with the FP64 formulas above: the optimiser-in-the-loop
+ * use the paper motivates (Sec. 1) and measures with 50 concurrent evaluations (Sec. 2), as a
+ * reference for the GPU driver.  Draws are counter based, SplitMix64's output for the state
+ * seed + (k + 1) * 0x9E3779B97F4A7C15, draw k = (g * np + i) * (D + 4) + slot for individual i
+ * of generation g: slots 0-2 choose r1, r2, r3 among the indices not yet taken (i first), as
+ * the v-th remaining index in increasing order with v = draw mod count; slot 3 the forced
+ * position draw mod D; slot 4 + j the crossover uniform (draw >> 11) 2^-53 of variable j.
+ * Trial: fma(F, x_r2 - x_r3, x_r1) clamped to [-100, 100] where the uniform is below CR or at the
+ * forced position, the target's value elsewhere; a trial whose value is not larger replaces
+ * its target.  pop (np x D) and fit (np) are updated in place over `generations` generations
+ * starting at generation gen0.  Returns the smallest |f_trial - f_target| / max(1, |f_target|)
+ * met in a selection (how close the closest decision was).
+ * ---------------------------------------------------------------------------------------- */
+static uint64_t orc_counter_draw(uint64_t seed, uint64_t k) {
+  return orc_mix64(seed + (k + 1u) * 0x9E3779B97F4A7C15ULL);
+}
+
+double orc_de_run(const orc_problem *p, int np, double F, double CR, uint64_t seed, uint64_t gen0, int generations,
+                  double *pop, double *fit) {
+  int D = p->dim;
+  double *trial = (double *)malloc(sizeof(double) * (size_t)np * (size_t)D);
+  double *ft = (double *)malloc(sizeof(double) * (size_t)np);
+  int *avail = (int *)malloc(sizeof(int) * (size_t)np);
+  double margin = INFINITY;
+  for (int gi = 0; gi < generations; ++gi) {
+    uint64_t g = gen0 + (uint64_t)gi;
+    for (int i = 0; i < np; ++i) {
+      uint64_t base = ((uint64_t)g * (uint64_t)np + (uint64_t)i) * (uint64_t)(D + 4);
+      /* indices still allowed, in increasing order; take i out first */
+      int navail = 0;
+      for (int a = 0; a < np; ++a)
+        if (a != i) avail[navail++] = a;
+      int r[3];
+      for (int t = 0; t < 3; ++t) {
+        int v = (int)(orc_counter_draw(seed, base + (uint64_t)t) % (uint64_t)navail);
+        r[t] = avail[v];
+        for (int a = v; a + 1 < navail; ++a) avail[a] = avail[a + 1];
+        --navail;
+      }
+      int jr = (int)(orc_counter_draw(seed, base + 3) % (uint64_t)D);
+      for (int j = 0; j < D; ++j) {
+        double u = (double)(orc_counter_draw(seed, base + 4 + (uint64_t)j) >> 11) * 0x1.0p-53;
+        double v = pop[(size_t)i * D + j];
+        if (u < CR || j == jr) {
+          v = fma(F, pop[(size_t)r[1] * D + j] - pop[(size_t)r[2] * D + j], pop[(size_t)r[0] * D + j]);
+          if (v < -100.0) v = -100.0;
+          if (v > 100.0) v = 100.0;
+        }
+        trial[(size_t)i * D + j] = v;
+      }
+    }
+    orc_evaluate(p, trial, np, ft, 1);
+    for (int i = 0; i < np; ++i) {
+      double m = fabs(ft[i] - fit[i]) / fmax(1.0, fabs(fit[i]));
+      if (m < margin) margin = m;
+      if (ft[i] <= fit[i]) {
+        memcpy(pop + (size_t)i * D, trial + (size_t)i * D, sizeof(double) * (size_t)D);
+        fit[i] = ft[i];
+      }
+    }
+  }
+  free(trial);
+  free(ft);
+  free(avail);
+  return margin;
+}

@@ -30,7 +30,7 @@ __all__ = [
     "initialize", "dispose", "func_evaluate", "func_evaluatef", "h_func_evaluate", "h_func_evaluatef",
     "set_stream", "set_mode", "define_basic", "define_hybrid", "define_composition", "get_problem",
     "generate_basic", "get_dim", "get_structure", "get_composition", "generate_structure",
-    "generate_composition", "last_error", "CurobError", "Batch",
+    "generate_composition", "last_error", "CurobError", "Batch", "DE",
 ]
 
 # dimension given to initialize, for the shape checks of the device calls (None: not initialised
@@ -262,6 +262,51 @@ def probe_mfma_bf16_tflops(reps: int = 5) -> float:
     tf = ctypes.c_double()
     check(lib.curob_probe_mfma_bf16(int(reps), ctypes.byref(tf)))
     return tf.value
+
+
+class DE:
+    """Differential evolution (DE/rand/1/bin) on the GPU around func_evaluate[f]
+    (curob_de_run): population, values, work space and the generation counter are device
+    tensors owned here.  run(k) enqueues k generations on torch's current stream; capture(k)
+    records k generations in one CUDA/HIP graph that replay() runs again (continuing from the
+    device generation counter)."""
+
+    def __init__(self, fid: int, pop, F: float = 0.5, CR: float = 0.9, seed: int = 0, fp64: bool = True):
+        import torch
+        want = torch.float64 if fp64 else torch.float32
+        if not (pop.is_cuda and pop.dtype == want and pop.is_contiguous() and pop.dim() == 2):
+            raise ValueError(f"pop must be a contiguous 2-D {want} CUDA tensor")
+        if pop.shape[1] != _current_dim():
+            raise ValueError("population rows must have the initialised dimension")
+        self.fid, self.F, self.CR, self.seed, self.fp64 = int(fid), float(F), float(CR), int(seed), bool(fp64)
+        self.pop = pop.clone()
+        self.np = int(pop.shape[0])
+        self.trial = torch.empty_like(self.pop)
+        self.ftrial = torch.empty(self.np, dtype=want, device=pop.device)
+        self.gen = torch.zeros(1, dtype=torch.int64, device=pop.device)
+        self.fit = (func_evaluate if fp64 else func_evaluatef)(self.fid, self.pop).clone()
+        self.graph = None
+
+    def run(self, generations: int) -> None:
+        check(lib.curob_set_stream(_torch_stream()))
+        check(lib.curob_de_run(self.fid, int(self.fp64), self.np, self.F, self.CR, self.seed, _ptr(self.pop),
+                               _ptr(self.fit), _ptr(self.trial), _ptr(self.ftrial), _ptr(self.gen), int(generations)))
+
+    def capture(self, generations: int) -> None:
+        """Records `generations` generations (trials, evaluation, selection) in one graph."""
+        import torch
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g, stream=s):
+                self.run(generations)
+        torch.cuda.current_stream().wait_stream(s)
+        check(lib.curob_set_stream(_torch_stream()))
+        self.graph = g
+
+    def replay(self) -> None:
+        self.graph.replay()
 
 
 class Batch:

@@ -24,6 +24,7 @@ MODE_SPLIT_BF16X3 = 2
 MODE_SPLIT_BF16X6 = 3
 CUSTOM_ID_MIN = 64
 CUSTOM_ID_MAX = 1023
+NOALLOC_SCRATCH_BYTES = 32 << 20
 
 EXPORTED = [
     "initialize", "dispose", "func_evaluate", "func_evaluatef", "h_func_evaluate", "h_func_evaluatef",
@@ -33,6 +34,7 @@ EXPORTED = [
     "curob_batch_configure", "curob_batch_shape", "curob_batch_tune", "curob_batch_destroy",
     "curob_probe_read", "curob_probe_mfma_bf16", "curob_get_dim", "curob_get_info", "curob_get_structure",
     "curob_get_composition", "curob_generate_info", "curob_generate_structure", "curob_generate_composition",
+    "func_evaluatef_noalloc", "curob_de_run",
 ]
 BATCH_KEY_BASE = 2048  # population i of a batch keys its random data like custom id 2048 + i
 
@@ -54,6 +56,8 @@ def _load():
         "dispose": (i32, []),
         "func_evaluate": (i32, [i32, vp, i32, vp]),
         "func_evaluatef": (i32, [i32, vp, i32, vp]),
+        "func_evaluatef_noalloc": (i32, [i32, vp, i32, vp]),
+        "curob_de_run": (i32, [i32, i32, i32, ctypes.c_double, ctypes.c_double, u64, vp, vp, vp, vp, vp, i32]),
         "h_func_evaluate": (i32, [i32, vp, i32, vp]),
         "h_func_evaluatef": (i32, [i32, vp, i32, vp]),
         "curob_set_stream": (i32, [vp]),

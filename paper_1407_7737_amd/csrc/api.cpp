@@ -17,7 +17,20 @@
 #include "problem.h"
 #include "tables.h"
 
+// Device memory of the allocation-free entry point func_evaluatef_noalloc: the tiled and
+// composition kernels' scratch (partial sums, pairwise z, packed operands, component values)
+// carved out of one file-scope array per device.  Host code never uses this name as an address:
+// it takes the device address from hipGetSymbolAddress once per device and passes that on.
+constexpr size_t kNoallocScratchBytes = CUROB_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
 namespace curob {
+
+hipError_t launch_de_trial(bool f64, const void *pop, void *trial, int np, int D, double F, double CR, uint64_t seed,
+                           const unsigned long long *gen, hipStream_t st);
+hipError_t launch_de_select(bool f64, void *pop, void *fit, const void *trial, const void *ftrial, int np, int D,
+                            unsigned long long *gen, hipStream_t st);
+
 namespace {
 
 struct Entry {
@@ -52,6 +65,9 @@ struct Context {
 
 Context g_ctx;
 std::string g_err;
+
+// device -> address of that device's copy of `scratch` (looked up once per device)
+std::map<int, void *> g_noalloc_scratch;
 
 int fail(int code, const char *fmt, ...) {
   char buf[512];
@@ -99,7 +115,7 @@ int prepare_entry(Entry &e) {
     return hip_fail(he, "uploading composite tables");
   }
   size_t pb = 0, zb = 0, gb = 0, kb = 0;
-  composite_scratch_needs(e.comp, pb, zb, gb, kb);
+  composite_scratch_needs(e.comp, kChunkRows, pb, zb, gb, kb);
   he = g_ctx.scratch.reserve(pb, zb, gb, kb);
   if (he != hipSuccess) return hip_fail(he, "allocating scratch");
   return CUROB_OK;
@@ -318,6 +334,15 @@ int initialize(int dim, int max_concurrency, unsigned long long seed) {
     free_context();
     return fail(CUROB_E_ARG, "%s", ex.what());
   }
+  if (g_noalloc_scratch.find(g_ctx.device) == g_noalloc_scratch.end()) {
+    void *ptr = nullptr;
+    he = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (he != hipSuccess || ptr == nullptr) {
+      free_context();
+      return hip_fail(he != hipSuccess ? he : hipErrorInvalidSymbol, "locating the static scratch");
+    }
+    g_noalloc_scratch[g_ctx.device] = ptr;
+  }
   he = hipEventCreateWithFlags(&g_ctx.scratch_done, hipEventDisableTiming);
   if (he != hipSuccess) {
     free_context();
@@ -344,6 +369,32 @@ int dispose(void) {
 
 int func_evaluate(int fid, const double *d_x, int n, double *d_out) { return evaluate(PATH_F64, fid, d_x, n, d_out); }
 
+int func_evaluatef_noalloc(int fid, const float *d_x, int n, float *d_out) {
+  Entry *e = nullptr;
+  int rc = check_eval_args(fid, d_x, n, d_out, &e);
+  if (rc != CUROB_OK || n == 0) return rc;
+  const int path = fp32_path(fid);
+  hipError_t he;
+  if (e->host.type == Problem::BASIC && e->dev[path].ready) {
+    // the resident kernel works without scratch
+    const DevProb &pb = e->dev[path].pb;
+    he = launch_resident(path, pb, d_x, d_out, n, resident_shape(path, pb, n, g_ctx.num_cu), g_ctx.stream);
+  } else if (e->comp.ready) {
+    auto it = g_noalloc_scratch.find(g_ctx.device);
+    if (it == g_noalloc_scratch.end()) return fail(CUROB_E_STATE, "no static scratch on device %d", g_ctx.device);
+    CompositeScratch sc;
+    if (!carve_scratch(e->comp, it->second, kNoallocScratchBytes, sc))
+      return fail(CUROB_E_CAPACITY, "function id %d needs more than the %zu-byte static scratch for %d rows", fid,
+                  kNoallocScratchBytes, kTileRows);
+    const bool split_auto = g_ctx.mode == CUROB_MODE_SPLIT;
+    he = launch_composite(path, split_auto, e->comp, d_x, d_out, n, g_ctx.num_cu, sc, g_ctx.stream);
+  } else {
+    return fail(CUROB_E_HIP, "function id %d has no device tables", fid);
+  }
+  if (he != hipSuccess) return hip_fail(he, "kernel launch");
+  return CUROB_OK;
+}
+
 int func_evaluatef(int fid, const float *d_x, int n, float *d_out) { return evaluate(fp32_path(fid), fid, d_x, n, d_out); }
 
 int h_func_evaluate(int fid, const double *h_x, int n, double *h_out) {
@@ -352,6 +403,28 @@ int h_func_evaluate(int fid, const double *h_x, int n, double *h_out) {
 
 int h_func_evaluatef(int fid, const float *h_x, int n, float *h_out) {
   return h_evaluate<float>(fp32_path(fid), fid, h_x, n, h_out);
+}
+
+int curob_de_run(int fid, int fp64, int np, double F, double CR, unsigned long long seed, void *d_pop, void *d_fit,
+                 void *d_trial, void *d_ftrial, unsigned long long *d_gen, int generations) {
+  Entry *e = nullptr;
+  int rc = check_eval_args(fid, d_pop, np, d_fit, &e);
+  if (rc != CUROB_OK) return rc;
+  if (np < 4) return fail(CUROB_E_ARG, "differential evolution needs np >= 4 (got %d)", np);
+  if (!d_trial || !d_ftrial || !d_gen) return fail(CUROB_E_ARG, "null pointer");
+  if (!(F > 0.0 && F <= 2.0) || !(CR >= 0.0 && CR <= 1.0))
+    return fail(CUROB_E_ARG, "F must be in (0, 2] and CR in [0, 1]");
+  if (generations < 0) return fail(CUROB_E_ARG, "generations must be >= 0");
+  const int path = fp64 ? PATH_F64 : fp32_path(fid);
+  for (int g = 0; g < generations; ++g) {
+    hipError_t he = launch_de_trial(fp64 != 0, d_pop, d_trial, np, g_ctx.dim, F, CR, seed, d_gen, g_ctx.stream);
+    if (he != hipSuccess) return hip_fail(he, "trial vectors");
+    rc = evaluate(path, fid, d_trial, np, d_ftrial);
+    if (rc != CUROB_OK) return rc;
+    he = launch_de_select(fp64 != 0, d_pop, d_fit, d_trial, d_ftrial, np, g_ctx.dim, d_gen, g_ctx.stream);
+    if (he != hipSuccess) return hip_fail(he, "selection");
+  }
+  return CUROB_OK;
 }
 
 int curob_set_stream(void *hip_stream) {

@@ -8,21 +8,23 @@
 
 namespace curob {
 
-hipError_t launch_tiled_split(int, const TiledProb &, const void *, void *, int, void *, void *, void *, hipStream_t);
-hipError_t launch_tiled_split6(int, const TiledProb &, const void *, void *, int, void *, void *, void *, hipStream_t);
-hipError_t launch_tiled_f32(int, const TiledProb &, const void *, void *, int, void *, void *, void *, hipStream_t);
-hipError_t launch_tiled_f64(int, const TiledProb &, const void *, void *, int, void *, void *, void *, hipStream_t);
+hipError_t launch_tiled_split(int, const TiledProb &, const void *, void *, int, int, void *, void *, void *,
+                              hipStream_t);
+hipError_t launch_tiled_split6(int, const TiledProb &, const void *, void *, int, int, void *, void *, void *,
+                               hipStream_t);
+hipError_t launch_tiled_f32(int, const TiledProb &, const void *, void *, int, int, void *, void *, void *, hipStream_t);
+hipError_t launch_tiled_f64(int, const TiledProb &, const void *, void *, int, int, void *, void *, void *, hipStream_t);
 hipError_t launch_blend(bool f64, const void *x, int n, int D, int nc, const double *o, const double *sigma,
                         const double *lambda, const double *bias, const void *G, int gstride, double fopt, void *out,
                         hipStream_t st);
 
-hipError_t launch_tiled(int path, int kind_hint, const TiledProb &tp, const void *x, void *out, int n, void *partials,
-                        void *zbuf, void *pack, hipStream_t st) {
+hipError_t launch_tiled(int path, int kind_hint, const TiledProb &tp, const void *x, void *out, int n, int cap,
+                        void *partials, void *zbuf, void *pack, hipStream_t st) {
   switch (path) {
-    case PATH_SPLIT: return launch_tiled_split(kind_hint, tp, x, out, n, partials, zbuf, pack, st);
-    case PATH_SPLIT6: return launch_tiled_split6(kind_hint, tp, x, out, n, partials, zbuf, pack, st);
-    case PATH_F32: return launch_tiled_f32(kind_hint, tp, x, out, n, partials, zbuf, pack, st);
-    case PATH_F64: return launch_tiled_f64(kind_hint, tp, x, out, n, partials, zbuf, pack, st);
+    case PATH_SPLIT: return launch_tiled_split(kind_hint, tp, x, out, n, cap, partials, zbuf, pack, st);
+    case PATH_SPLIT6: return launch_tiled_split6(kind_hint, tp, x, out, n, cap, partials, zbuf, pack, st);
+    case PATH_F32: return launch_tiled_f32(kind_hint, tp, x, out, n, cap, partials, zbuf, pack, st);
+    case PATH_F64: return launch_tiled_f64(kind_hint, tp, x, out, n, cap, partials, zbuf, pack, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -140,14 +142,14 @@ hipError_t build_composite(const Problem &p, CompositeDev &cd, std::string &err)
   return hipSuccess;
 }
 
-void composite_scratch_needs(const CompositeDev &cd, size_t &pb, size_t &zb, size_t &gb, size_t &kb) {
+void composite_scratch_needs(const CompositeDev &cd, int rows, size_t &pb, size_t &zb, size_t &gb, size_t &kb) {
   pb = zb = gb = kb = 0;
   auto acc_tiled = [&](const TiledDev (&t)[PATH_COUNT]) {
     for (int path = 0; path < PATH_COUNT; ++path)
       if (t[path].ready) {
-        pb = std::max(pb, tiled_partials_bytes(t[path].tp, path));
-        zb = std::max(zb, tiled_z_bytes(t[path].tp, path));
-        kb = std::max(kb, tiled_pack_bytes(t[path].tp, path));
+        pb = std::max(pb, tiled_partials_bytes(t[path].tp, path, rows));
+        zb = std::max(zb, tiled_z_bytes(t[path].tp, path, rows));
+        kb = std::max(kb, tiled_pack_bytes(t[path].tp, path, rows));
       }
   };
   if (!cd.ready) return;
@@ -157,20 +159,47 @@ void composite_scratch_needs(const CompositeDev &cd, size_t &pb, size_t &zb, siz
   }
   for (const auto &c : cd.comps)
     if (!c.resident) acc_tiled(c.tiled);
-  gb = static_cast<size_t>(cd.comps.size()) * kChunkRows * sizeof(double);
+  gb = static_cast<size_t>(cd.comps.size()) * rows * sizeof(double);
+}
+
+bool carve_scratch(const CompositeDev &cd, void *base, size_t bytes, CompositeScratch &sc) {
+  auto up256 = [](size_t v) { return (v + 255) & ~static_cast<size_t>(255); };
+  for (int rows = kChunkRows; rows >= kTileRows; rows -= kTileRows) {
+    size_t pb, zb, gb, kb;
+    composite_scratch_needs(cd, rows, pb, zb, gb, kb);
+    if (up256(pb) + up256(zb) + up256(gb) + up256(kb) > bytes) continue;
+    unsigned char *p = static_cast<unsigned char *>(base);
+    sc = CompositeScratch{};
+    sc.cap = rows;
+    sc.partials = p;
+    sc.partials_bytes = pb;
+    p += up256(pb);
+    sc.zbuf = p;
+    sc.zbuf_bytes = zb;
+    p += up256(zb);
+    sc.gbuf = p;
+    sc.gbuf_bytes = gb;
+    p += up256(gb);
+    sc.pack = p;
+    sc.pack_bytes = kb;
+    return true;
+  }
+  return false;
 }
 
 hipError_t launch_composite(int path, bool split_auto, const CompositeDev &cd, const void *x, void *out, int n,
                             int num_cu, CompositeScratch &sc, hipStream_t st) {
   if (!cd.ready) return hipErrorNotSupported;
   const size_t esz = path == PATH_F64 ? 8 : 4;
-  for (int c0 = 0; c0 < n; c0 += kChunkRows) {
-    const int ch = std::min(kChunkRows, n - c0);
+  const int cap = sc.cap;
+  if (cap < kTileRows || cap % kTileRows != 0) return hipErrorInvalidValue;
+  for (int c0 = 0; c0 < n; c0 += cap) {
+    const int ch = std::min(cap, n - c0);
     const unsigned char *xc = static_cast<const unsigned char *>(x) + static_cast<size_t>(c0) * cd.dim * esz;
     unsigned char *oc = static_cast<unsigned char *>(out) + static_cast<size_t>(c0) * esz;
     hipError_t e;
     if (!cd.is_composition) {
-      e = launch_tiled(path, cd.kind_hint, cd.tiled[path].tp, xc, oc, ch, sc.partials, sc.zbuf, sc.pack, st);
+      e = launch_tiled(path, cd.kind_hint, cd.tiled[path].tp, xc, oc, ch, cap, sc.partials, sc.zbuf, sc.pack, st);
       if (e != hipSuccess) return e;
       continue;
     }
@@ -179,18 +208,18 @@ hipError_t launch_composite(int path, bool split_auto, const CompositeDev &cd, c
       const CompositeDev::Component &cc = cd.comps[i];
       int cp = path;
       if (split_auto && is_split(path)) cp = cc.six ? PATH_SPLIT6 : PATH_SPLIT;
-      unsigned char *gi = static_cast<unsigned char *>(sc.gbuf) + static_cast<size_t>(i) * kChunkRows * esz;
+      unsigned char *gi = static_cast<unsigned char *>(sc.gbuf) + static_cast<size_t>(i) * cap * esz;
       if (cc.resident) {
         const DevProb &pb = cc.res[cp].pb;
         e = launch_resident(cp, pb, xc, gi, ch, resident_shape(cp, pb, ch, num_cu), st);
       } else {
         const int hint = cc.tiled[cp].tp.nsegs == 1 ? cc.tiled[cp].tp.segs[0].kind : -1;
-        e = launch_tiled(cp, hint, cc.tiled[cp].tp, xc, gi, ch, sc.partials, sc.zbuf, sc.pack, st);
+        e = launch_tiled(cp, hint, cc.tiled[cp].tp, xc, gi, ch, cap, sc.partials, sc.zbuf, sc.pack, st);
       }
       if (e != hipSuccess) return e;
     }
-    e = launch_blend(path == PATH_F64, xc, ch, cd.dim, nc, cd.o64, cd.sig, cd.lam, cd.cb, sc.gbuf, kChunkRows, cd.fopt,
-                     oc, st);
+    e = launch_blend(path == PATH_F64, xc, ch, cd.dim, nc, cd.o64, cd.sig, cd.lam, cd.cb, sc.gbuf, cap, cd.fopt, oc,
+                     st);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

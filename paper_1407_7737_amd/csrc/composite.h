@@ -34,13 +34,16 @@ struct CompositeDev {
   void release();
 };
 
-// Scratch shared by all composite evaluations of a context (one chunk of rows).
+// Scratch shared by all composite evaluations of a context: buffers for a chunk of `cap` rows
+// (rows are evaluated in passes of cap).  reserve/release manage library-allocated buffers;
+// carve_scratch points the four buffers into caller-provided memory instead.
 struct CompositeScratch {
   void *partials = nullptr;
   void *zbuf = nullptr;
   void *gbuf = nullptr;
   void *pack = nullptr;
   size_t partials_bytes = 0, zbuf_bytes = 0, gbuf_bytes = 0, pack_bytes = 0;
+  int cap = kChunkRows;
   hipError_t reserve(size_t pb, size_t zb, size_t gb, size_t kb);
   void release();
 };
@@ -49,8 +52,13 @@ struct CompositeScratch {
 // kernel's range need nothing here.
 hipError_t build_composite(const Problem &p, CompositeDev &cd, std::string &err);
 
-// Scratch sizes the problem needs.
-void composite_scratch_needs(const CompositeDev &cd, size_t &pb, size_t &zb, size_t &gb, size_t &kb);
+// Scratch sizes the problem needs for chunks of `rows` rows.
+void composite_scratch_needs(const CompositeDev &cd, int rows, size_t &pb, size_t &zb, size_t &gb, size_t &kb);
+
+// Points sc into the `bytes` of device memory at base (256-byte aligned), with the largest chunk
+// of rows (a multiple of kTileRows, at most kChunkRows) whose buffers fit.  Returns false when
+// not even kTileRows rows fit.  Nothing is allocated.
+bool carve_scratch(const CompositeDev &cd, void *base, size_t bytes, CompositeScratch &sc);
 
 // Evaluates n rows of x into out.  path is the arithmetic of the call; in split mode
 // (split_auto) the components of a composition pick three or six products per formula.

@@ -438,7 +438,7 @@ __device__ __forceinline__ void mtile_epilogue(const TiledProb &tp, const TiledS
 template <int P, int KIND>
 __global__ __launch_bounds__(kGemmThreads) void k_tiled_gemm(TiledProb tp, const unsigned char *pack, int n,
                                                     int ntiles, typename Types<P>::T *__restrict__ partials,
-                                                    typename Types<P>::T *__restrict__ zbuf) {
+                                                    typename Types<P>::T *__restrict__ zbuf, int pstride) {
   using T = typename Types<P>::T;
   using Acc4 = typename Types<P>::Acc4;
   constexpr int NP = pack_parts<P>();
@@ -539,7 +539,7 @@ __global__ __launch_bounds__(kGemmThreads) void k_tiled_gemm(TiledProb tp, const
       for (int k = 0; k < 3; ++k) acc_merge(a, k, src[2 * k], src[2 * k + 1]);
       a.p *= src[6];
     }
-    T *dst = partials + (static_cast<size_t>(gi) * kChunkRows + row0 + tid) * kPartialSlots;
+    T *dst = partials + (static_cast<size_t>(gi) * pstride + row0 + tid) * kPartialSlots;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       dst[2 * k] = a.s[k];
@@ -634,7 +634,7 @@ __global__ __launch_bounds__(256) void k_rowwise(TiledProb tp, const typename Ty
 template <int P>
 __global__ __launch_bounds__(256) void k_tiled_finalize(TiledProb tp, const typename Types<P>::T *__restrict__ partials,
                                                         const typename Types<P>::T *__restrict__ zbuf, int n,
-                                                        typename Types<P>::T *__restrict__ out) {
+                                                        typename Types<P>::T *__restrict__ out, int pstride) {
   using T = typename Types<P>::T;
   (void)zbuf;
   // one thread per row (problems without pair terms): the partial slots of consecutive rows
@@ -648,7 +648,7 @@ __global__ __launch_bounds__(256) void k_tiled_finalize(TiledProb tp, const type
     a.init();
     if (live) {
       for (int g = sg.g0; g < sg.g1; ++g) {
-        const T *src = partials + (static_cast<size_t>(g) * kChunkRows + row) * kPartialSlots;
+        const T *src = partials + (static_cast<size_t>(g) * pstride + row) * kPartialSlots;
         T v[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) v[k] = src[k];
@@ -704,7 +704,7 @@ __device__ __forceinline__ void pair_terms(const TiledProb &tp, const TiledSeg &
 template <int P>
 __global__ __launch_bounds__(256) void k_tiled_finalize_pairs(TiledProb tp, const typename Types<P>::T *__restrict__ partials,
                                                         const typename Types<P>::T *__restrict__ zbuf, int n,
-                                                        typename Types<P>::T *__restrict__ out) {
+                                                        typename Types<P>::T *__restrict__ out, int pstride) {
   using T = typename Types<P>::T;
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -736,7 +736,7 @@ __global__ __launch_bounds__(256) void k_tiled_finalize_pairs(TiledProb tp, cons
       for (int g0 = sg.g0; g0 < sg.g1; g0 += 64) {
         const int g = g0 + lane;
         if (g < sg.g1) {
-          const T *src = partials + (static_cast<size_t>(g) * kChunkRows + row) * kPartialSlots;
+          const T *src = partials + (static_cast<size_t>(g) * pstride + row) * kPartialSlots;
           T v[8];
 #pragma unroll
           for (int k = 0; k < 8; ++k) v[k] = src[k];
@@ -793,14 +793,16 @@ inline int pack_stride(int D) {
   return sx;
 }
 
-// pack, GEMM + formula, finalize for rows [0, n) (n <= kChunkRows) of one path
+// pack, GEMM + formula, finalize for rows [0, n) of one path; the scratch holds `cap` rows
+// (n <= cap, cap a multiple of the GEMM's row tile): the partial sums of output group g start
+// at row g * cap, the pack and z buffers hold cap rows
 template <int P, int... Ks>
-hipError_t launch_tiled_path(int kind_hint, const TiledProb &tp, const void *x, void *out, int n, void *partials,
-                             void *zbuf, void *pack, hipStream_t st, std::integer_sequence<int, Ks...>) {
+hipError_t launch_tiled_path(int kind_hint, const TiledProb &tp, const void *x, void *out, int n, int cap,
+                             void *partials, void *zbuf, void *pack, hipStream_t st, std::integer_sequence<int, Ks...>) {
   static const void *const gemm[] = {reinterpret_cast<const void *>(&k_tiled_gemm<P, Ks>)...};
   const void *fn = (kind_hint >= 0 && kind_hint < K_COUNT) ? gemm[kind_hint]
                                                            : reinterpret_cast<const void *>(&k_tiled_gemm<P, -1>);
-  if (n > kChunkRows) return hipErrorInvalidValue;
+  if (n > cap || cap % kTileRows != 0) return hipErrorInvalidValue;
   if (tp.rowwise) {
     if (kind_hint < 0 || kind_hint >= K_COUNT) return hipErrorInvalidValue;
     static const void *const rowwise[] = {reinterpret_cast<const void *>(&k_rowwise<P, Ks>)...};
@@ -832,12 +834,12 @@ hipError_t launch_tiled_path(int kind_hint, const TiledProb &tp, const void *x, 
   void *pargs[] = {&arg, &xa, &na, &Ra, &SXa, &va, &pka};
   hipError_t e = hipLaunchKernel(pk, dim3(tiles * kTileRows / R), dim3(256), pargs, static_cast<size_t>(lds), st);
   if (e != hipSuccess) return e;
-  int ta = tiles;
-  void *gargs[] = {&arg, &pkc, &na, &ta, &pa, &za};
+  int ta = tiles, ca = cap;
+  void *gargs[] = {&arg, &pkc, &na, &ta, &pa, &za, &ca};
   const int rounds = (tiles + kNumXcd - 1) / kNumXcd;
   e = hipLaunchKernel(fn, dim3(tp.ngroups * rounds * kNumXcd), dim3(kGemmThreads), gargs, 0, st);
   if (e != hipSuccess) return e;
-  void *fargs[] = {&arg, &pa, &za, &na, &oa};
+  void *fargs[] = {&arg, &pa, &za, &na, &oa, &ca};
   if (tp.any_pairwise)
     return hipLaunchKernel(reinterpret_cast<const void *>(&k_tiled_finalize_pairs<P>), dim3((n + 3) / 4), dim3(256),
                            fargs, 0, st);

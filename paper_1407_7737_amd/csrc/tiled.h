@@ -72,14 +72,15 @@ struct TiledDev {
 // Builds and uploads the tiled tables of a basic or hybrid problem for one path.
 hipError_t build_tiled(const Problem &p, int path, TiledDev &td, std::string &err);
 
-// Scratch the tiled kernels need for one chunk of rows: partial sums, (pairwise) z and the
+// Scratch the tiled kernels need for a chunk of `rows` rows: partial sums, (pairwise) z and the
 // packed B operands (bytes per packed position and row: 2 per bf16 term, 4 FP32, 8 FP64).
-size_t tiled_partials_bytes(const TiledProb &tp, int path);
-size_t tiled_z_bytes(const TiledProb &tp, int path);
-size_t tiled_pack_bytes(const TiledProb &tp, int path);
+size_t tiled_partials_bytes(const TiledProb &tp, int path, int rows);
+size_t tiled_z_bytes(const TiledProb &tp, int path, int rows);
+size_t tiled_pack_bytes(const TiledProb &tp, int path, int rows);
 
-// Evaluates rows [0, n) of x (n <= kChunkRows) into out using the scratch buffers.
-hipError_t launch_tiled(int path, int kind_hint, const TiledProb &tp, const void *x, void *out, int n, void *partials,
-                        void *zbuf, void *pack, hipStream_t st);
+// Evaluates rows [0, n) of x into out using scratch buffers sized for cap rows (n <= cap, cap a
+// multiple of kTileRows).
+hipError_t launch_tiled(int path, int kind_hint, const TiledProb &tp, const void *x, void *out, int n, int cap,
+                        void *partials, void *zbuf, void *pack, hipStream_t st);
 
 }  // namespace curob

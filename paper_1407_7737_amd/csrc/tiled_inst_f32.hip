@@ -3,9 +3,9 @@
 
 namespace curob {
 
-hipError_t launch_tiled_f32(int kind_hint, const TiledProb &tp, const void *x, void *out, int n, void *partials,
-                         void *zbuf, void *pack, hipStream_t st) {
-  return tiled::launch_tiled_path<PATH_F32>(kind_hint, tp, x, out, n, partials, zbuf, pack, st,
+hipError_t launch_tiled_f32(int kind_hint, const TiledProb &tp, const void *x, void *out, int n, int cap,
+                         void *partials, void *zbuf, void *pack, hipStream_t st) {
+  return tiled::launch_tiled_path<PATH_F32>(kind_hint, tp, x, out, n, cap, partials, zbuf, pack, st,
                                           std::make_integer_sequence<int, K_COUNT>{});
 }
 

@@ -256,19 +256,19 @@ hipError_t build_tiled(const Problem &p, int path, TiledDev &td, std::string &er
   return hipSuccess;
 }
 
-size_t tiled_partials_bytes(const TiledProb &tp, int path) {
+size_t tiled_partials_bytes(const TiledProb &tp, int path, int rows) {
   const size_t esz = path == PATH_F64 ? 8 : 4;
-  return static_cast<size_t>(tp.ngroups) * kChunkRows * kPartialSlots * esz;
+  return tp.rowwise ? 0 : static_cast<size_t>(tp.ngroups) * rows * kPartialSlots * esz;
 }
 
-size_t tiled_pack_bytes(const TiledProb &tp, int path) {
+size_t tiled_pack_bytes(const TiledProb &tp, int path, int rows) {
   const size_t bpp = is_split(path) ? 2 * split_terms(path) : (path == PATH_F64 ? 8 : 4);
-  return static_cast<size_t>(kChunkRows) * tp.Dp * bpp;
+  return tp.rowwise ? 0 : static_cast<size_t>(rows) * tp.Dp * bpp;
 }
 
-size_t tiled_z_bytes(const TiledProb &tp, int path) {
+size_t tiled_z_bytes(const TiledProb &tp, int path, int rows) {
   const size_t esz = path == PATH_F64 ? 8 : 4;
-  return tp.any_pairwise ? static_cast<size_t>(kChunkRows) * tp.Dp * esz : 0;
+  return tp.any_pairwise && !tp.rowwise ? static_cast<size_t>(rows) * tp.Dp * esz : 0;
 }
 
 }  // namespace curob
