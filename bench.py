@@ -45,6 +45,19 @@ NAMES = {0: "sphere", 2: "elliptic", 9: "griewank", 10: "rastrigin_u", 11: "rast
 RESIDENT_KERNEL = {0: (0, 0, 0), 2: (0, 0, 1), 9: (0, 5, 1), 10: (0, 6, 0), 11: (0, 6, 1), 14: (0, 9, 1),
                    16: (3, 10, 1), 19: (0, 13, 1)}
 HBM_PEAK_GBS = 8000.0
+# The paper's own figures (Sec. 2, Tab. 2 single precision and Tab. 3 double precision): speedup of
+# its CUDA implementation over the CPU-based CEC'14 code, 50 concurrent evaluations x 1000 runs,
+# at its largest dimension (96).  Quoted as context only: other hardware, other baseline.
+PAPER_CONTEXT = {
+    "hardware": "Intel Core i5-2310 CPU + NVIDIA GeForce GTX 560 Ti, Windows 7 SP1 x64, CUDA 5.5",
+    "workload": "50 evaluations per call x 1000 runs, uniform random data, D in {10, 32, 64, 96}",
+    "baseline": "CPU CEC'14 benchmark code (not available here)",
+    "speedup_d96_fp32": {"griewank": 11.13, "rastrigin_u": 1.82, "rastrigin": 9.98, "rosenbrock": 8.75,
+                         "schwefel": 14.38, "ackley": 11.32},
+    "speedup_d96_fp64": {"griewank": 9.72, "rastrigin_u": 1.78, "rastrigin": 9.62, "rosenbrock": 7.87,
+                         "schwefel": 11.91, "ackley": 9.75},
+    "note": "no absolute rates are published; these ratios do not compare with this build's numbers",
+}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_d100_n262144.json")
 KERNEL_SOURCES = ["eval_resident.h", "formulas.h", "devprob.h", "kernels.h"]
 COPY_PROBE_BYTES = N * DIM * 4  # the probe reads the FP32 population once and writes it once
@@ -77,10 +90,42 @@ def measured_traffic(fid: int):
     return None if k is None else k.get("hbm_bytes_per_launch")
 
 
+def host_cpu() -> dict:
+    """CPU model and logical CPU count of the host (lscpu's model name, nproc)."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.lower().startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"model_name": model, "nproc": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
+
+
+def cpu_single_thread(x32: np.ndarray, budget_s: float = 4.0) -> dict:
+    """The oracle on one thread (the plain, slow figure), on consecutive 512-row chunks."""
+    import oracle
+    probs = {fid: oracle.basic(fid, DIM, 0) for fid in FIDS}
+    rows, t, start = 0, 0.0, 0
+    while t < budget_s:
+        sample = x32[start:start + 512].astype(np.float64)
+        t0 = time.perf_counter()
+        for fid in FIDS:
+            probs[fid](sample, threads=1)
+        t += time.perf_counter() - t0
+        rows += 512
+        start = (start + 512) % (N - 512)
+    return {"value": rows * len(FIDS) / t, "unit": "evals/s", "cores": 1,
+            "sample": f"{rows} rows x {len(FIDS)} formulas in {t:.1f} s"}
+
+
 def cpu_baseline(x32: np.ndarray, gpu: dict, budget_s: float = 12.0):
     """The oracle as it stands, on the host cores, on a bounded sample of the same rows: chunks
     of the population (wrapping around) on all measured formulas until about budget_s seconds
-    of CPU work have been timed."""
+    of CPU work have been timed.  Threads: the CPU share of one GPU on the box (16; OpenMP's
+    default there), or fewer where the host has fewer."""
     import oracle
     threads = max(1, min(os.cpu_count() or 1, oracle.threads_available(), 16))
     probs = {fid: oracle.basic(fid, DIM, 0) for fid in FIDS}
@@ -116,6 +161,8 @@ def cpu_baseline(x32: np.ndarray, gpu: dict, budget_s: float = 12.0):
                   f"each of the {len(FIDS)} formulas, {total_rows} evaluations in {t_total:.1f} s; FP64 "
                   f"dense-rotation oracle, OpenMP over rows",
         "errors_vs_oracle": errors,
+        "single_thread": cpu_single_thread(x32),
+        "host": host_cpu(),
     }
 
 
@@ -133,24 +180,70 @@ def event_time_ms(torch, fn, reps: int, warmup: int = 2) -> float:
     return a.elapsed_time(b) / reps
 
 
+MFMA_BF16_PEAK_TFLOPS = 2500.0  # dense BF16 matrix peak (split paths)
+MFMA_FP32_PEAK_TFLOPS = 157.3   # FP32 matrix/vector peak (the plain FP32 mode's 16x16x4 FP32 MFMA)
+# formulas the default split mode evaluates with six BF16 products (at n variables)
+SIX = {3, 7, 8, 12, 13, 16, 17}
+
+
+def products(base: int, n: int) -> int:
+    return 6 if base in SIX or (base == 14 and n < 10) or (base == 2 and n < 50) else 3
+
+
+def rotation_work(c, pid: int, comp: int = -1):
+    """(sum of n_k^2 over the rotation blocks, BF16 products per term) of a basic or hybrid
+    problem in the default split mode, from the library's exported structure."""
+    st = c.get_structure(pid, comp)
+    sizes = [int(v) for v in st["sizes"]]
+    nsq = sum(v * v for v in sizes)
+    if st["type"] == "hybrid":
+        prods = 6 if any(products(int(b), int(n)) == 6 for b, n in zip(st["bases"], sizes)) else 3
+    else:
+        prods = products(int(st["bases"][0]), len(st["o"]))
+    return nsq, prods
+
+
+def mfma_frac(flops_per_row: float, rows: int, ms: float, peak_tflops: float) -> float:
+    return flops_per_row * rows / (ms * 1e-3) / (peak_tflops * 1e12)
+
+
 def secondary(torch, c, reps: int = 10) -> dict:
-    """The other workload shapes, timed briefly (kernel time from HIP events)."""
+    """The other workload shapes, timed briefly (kernel time from HIP events).  Rotation work is
+    algorithmic: 2 x sum n_k^2 multiply-adds per row over the nonzero blocks (no padding), times
+    the BF16 products per term (3 or 6) on the split path, once on the plain FP32 path."""
     from paper_1407_7737_amd.inputs import batch_params, composition_params, hybrid_params, population
     out = {}
     dev = torch.device("cuda:0")
-    # D = 1000, N = 2^18: the same eight formulas on the tiled path
+    # D = 1000, N = 2^18: the same eight formulas on the tiled path, default split mode and the
+    # plain FP32 mode
     d, n = 1000, 1 << 18
     c.initialize(d, n, 0)
     try:
         x = torch.from_numpy(population(n, d, seed=0, dtype=np.float32)).to(dev)
         o = torch.empty(n, dtype=torch.float32, device=dev)
-        per = {}
+        per, per32, frac, frac32 = {}, {}, {}, {}
         for fid in FIDS:
             per[NAMES[fid]] = event_time_ms(torch, lambda: c.func_evaluatef(fid, x, out=o), reps)
+        c.set_mode(c.MODE_FP32)
+        for fid in FIDS:
+            per32[NAMES[fid]] = event_time_ms(torch, lambda: c.func_evaluatef(fid, x, out=o), reps)
+        c.set_mode(c.MODE_SPLIT)
+        for fid in FIDS:
+            nsq, prods = rotation_work(c, fid)
+            if nsq == 0:
+                continue  # unrotated: no matrix work, bound by HBM
+            frac[NAMES[fid]] = {"products": prods, "flops_per_row": 2 * nsq * prods,
+                                "mfma_frac": mfma_frac(2 * nsq * prods, n, per[NAMES[fid]], MFMA_BF16_PEAK_TFLOPS)}
+            frac32[NAMES[fid]] = mfma_frac(2 * nsq, n, per32[NAMES[fid]], MFMA_FP32_PEAK_TFLOPS)
         tot = sum(per.values())
         out["d1000_n262144"] = {"evals_per_s": n * len(FIDS) / (tot * 1e-3), "ms_per_function": per,
                                 "hbm_frac_per_function": {k: n * (d * 4 + 4) / (v * 1e-3) / 1e9 / HBM_PEAK_GBS
-                                                          for k, v in per.items()}}
+                                                          for k, v in per.items()},
+                                "mfma_bf16_frac_per_function": frac,
+                                "fp32_mode_ms_per_function": per32,
+                                "fp32_mode_evals_per_s": n * len(FIDS) / (sum(per32.values()) * 1e-3),
+                                "fp32_mode_frac_of_157tf_per_function": frac32,
+                                "sum_nk2": rotation_work(c, 11)[0]}
         del x
         # hybrid and composition at D = 1000, N = 16384
         m = 16384
@@ -162,9 +255,19 @@ def secondary(torch, c, reps: int = 10) -> dict:
         c.define_composition(101, cb, sig, lam, bias)
         th = event_time_ms(torch, lambda: c.func_evaluatef(100, xh, out=oh), reps)
         tc = event_time_ms(torch, lambda: c.func_evaluatef(101, xh, out=oh), reps)
+        hn, hp = rotation_work(c, 100)
+        cflops = 0
+        for i in range(len(cb)):
+            cn, cp = rotation_work(c, 101, i)
+            cflops += 2 * cn * cp
         out["hybrid_d1000_n16384"] = {"evals_per_s": m / (th * 1e-3), "ms": th, "groups": len(bases),
-                                      "bases": bases}
-        out["composition_d1000_n16384"] = {"evals_per_s": m / (tc * 1e-3), "ms": tc, "components": len(cb)}
+                                      "bases": bases, "flops_per_row": 2 * hn * hp, "products": hp,
+                                      "mfma_frac": mfma_frac(2 * hn * hp, m, th, MFMA_BF16_PEAK_TFLOPS),
+                                      "hbm_frac": m * (d * 4 + 4) / (th * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        out["composition_d1000_n16384"] = {"evals_per_s": m / (tc * 1e-3), "ms": tc, "components": len(cb),
+                                           "flops_per_row": cflops,
+                                           "mfma_frac": mfma_frac(cflops, m, tc, MFMA_BF16_PEAK_TFLOPS),
+                                           "hbm_frac": m * (d * 4 + 4) / (tc * 1e-3) / 1e9 / HBM_PEAK_GBS}
     finally:
         c.dispose()
     # 64 batched populations
@@ -181,10 +284,26 @@ def secondary(torch, c, reps: int = 10) -> dict:
         tuned = b.tune(reps=20)
         t_graph = event_time_ms(torch, b.run, 50)
         t_direct = event_time_ms(torch, b.run_direct, 50)
+        # 16 persistent launches captured in one graph (e.g. 16 consecutive batches of an
+        # optimiser), replayed: the per-launch cost against 16 direct launches back to back
+        g16 = torch.cuda.CUDAGraph()
+        s16 = torch.cuda.Stream()
+        s16.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s16):
+            with torch.cuda.graph(g16, stream=s16):
+                for _ in range(16):
+                    b.run_direct()
+        torch.cuda.current_stream().wait_stream(s16)
+        c.set_stream(torch.cuda.current_stream())
+        t_g16 = event_time_ms(torch, g16.replay, 20) / 16
+        t_d16 = event_time_ms(torch, lambda: [b.run_direct() for _ in range(16)], 20) / 16
+        del g16
         b.close()
         rows = int(sum(counts))
         out["batch_64"] = {"rows": rows, "graph_ms": t_graph, "direct_ms": t_direct, "untuned_graph_ms": t_default,
-                           "evals_per_s": rows / (t_graph * 1e-3), "tuned_shape": tuned,
+                           "graph16_ms_per_launch": t_g16, "direct16_ms_per_launch": t_d16,
+                           "evals_per_s": rows / (t_graph * 1e-3),
+                           "evals_per_s_graph16": rows / (t_g16 * 1e-3), "tuned_shape": tuned,
                            "default_shape": default_shape}
     finally:
         c.dispose()
@@ -200,7 +319,36 @@ def secondary(torch, c, reps: int = 10) -> dict:
             c.dispose()
     out["batch_64"]["one_call_per_population_ms"] = per_call
     out["latency_n50"] = latency_small(torch, c)
+    out["de_n50"] = de_generations(torch, c)
     return out
+
+
+def de_generations(torch, c, gens: int = 100) -> dict:
+    """An optimiser in the loop, the paper's own setting (50 candidates per evaluation call):
+    DE/rand/1/bin generations (trial vectors, evaluation, selection) on rotated Rastrigin,
+    captured 100 at a time in one graph; time per generation of the replayed graph."""
+    from paper_1407_7737_amd.inputs import population
+    res = {}
+    for d in (10, 32, 64, 96):
+        c.initialize(d, 64, 0)
+        try:
+            row = {}
+            for fp64 in (False, True):
+                dt = np.float64 if fp64 else np.float32
+                de = c.DE(11, torch.from_numpy(population(50, d, seed=d).astype(dt)).cuda(), seed=1, fp64=fp64)
+                de.capture(gens)
+                de.replay()
+                torch.cuda.synchronize()
+                ms = event_time_ms(torch, de.replay, 5, warmup=1)
+                row["fp64_us_per_generation" if fp64 else "fp32_us_per_generation"] = ms * 1e3 / gens
+                row["fp64_best" if fp64 else "fp32_best"] = float(de.fit.min().item())
+                del de
+            res[f"d{d}"] = row
+        finally:
+            torch.cuda.synchronize()
+            c.set_stream(None)
+            c.dispose()
+    return res
 
 
 def latency_small(torch, c, calls: int = 100) -> dict:
@@ -419,6 +567,115 @@ def sq_summary(p1_dir: str, p2_dir: str) -> None:
     print("\n".join(lines))
 
 
+PROFILE_ROWS = 1 << 16  # one pass of the tiled path
+
+
+def profile_d1000(torch, c, reps: int = 3) -> None:
+    """The D = 1000 workloads alone, for rocprofv3 runs: the eight formulas on one 65536-row
+    pass (default split mode), the hybrid and the composition at N = 16384, `reps` launches
+    each, then the copy probe (torch.neg over the 65536-row population) that scales the
+    byte counters."""
+    from paper_1407_7737_amd.inputs import composition_params, hybrid_params, population
+    d, n, m = 1000, PROFILE_ROWS, 16384
+    c.initialize(d, n, 0)
+    try:
+        x = torch.from_numpy(population(n, d, seed=0, dtype=np.float32)).cuda()
+        o = torch.empty(n, dtype=torch.float32, device="cuda")
+        for fid in FIDS:
+            for _ in range(reps):
+                c.func_evaluatef(fid, x, out=o)
+        bases, props = hybrid_params(d, seed=0)
+        c.define_hybrid(100, bases, props)
+        cb, sig, lam, bias = composition_params(seed=0)
+        c.define_composition(101, cb, sig, lam, bias)
+        for pid in (100, 101):
+            for _ in range(reps):
+                c.func_evaluatef(pid, x[:m], out=o[:m])
+        torch.cuda.synchronize()
+        buf = torch.empty_like(x)
+        for _ in range(reps):
+            torch.neg(x, out=buf)
+        torch.cuda.synchronize()
+    finally:
+        c.dispose()
+    print(json.dumps({"profiled": "d1000", "rows": n, "reps": reps}), flush=True)
+
+
+def tiled_summary(trace_dir: str, fetch_dir: str, write_dir: str, sq1_dir: str, sq2_dir: str) -> None:
+    """Per-kernel durations, HBM traffic and SQ counters of the D = 1000 workloads from five
+    rocprofv3 runs of `bench.py --profile-d1000`; writes profiles/tiled_d1000_kernels.txt."""
+    def counters(d):
+        vals = {}
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for row in csv.DictReader(open(f)):
+                vals.setdefault(row["Kernel_Name"], {}).setdefault(row["Counter_Name"], []).append(
+                    float(row["Counter_Value"]))
+        return vals
+
+    def short(name):
+        m = re.search(r"(k_\w+)<([^>]*)>", name)
+        if m:
+            return m.group(1) + "<" + m.group(2).replace(" ", "") + ">"
+        m = re.search(r"(k_\w+)ILi(-?\d+)ELi(-?\d+)E", name) or re.search(r"(k_\w+)ILi(-?\d+)E", name)
+        if m:
+            return m.group(1) + "<" + ",".join(m.groups()[1:]) + ">"
+        m = re.search(r"(k_\w+)", name)
+        return m.group(1) if m else ("neg" if "neg" in name.lower() else None)
+
+    dur = {}
+    for r in csv.DictReader(open(os.path.join(trace_dir, "run_kernel_stats.csv"))):
+        k = short(r["Name"])
+        if k:
+            a = dur.setdefault(k, [0, 0.0])
+            a[0] += int(r["Calls"])
+            a[1] += float(r["TotalDurationNs"])
+    merged = {}
+    for d in (fetch_dir, write_dir, sq1_dir, sq2_dir):
+        for name, cs in counters(d).items():
+            k = short(name)
+            if k:
+                for cn, v in cs.items():
+                    merged.setdefault(k, {}).setdefault(cn, []).extend(v)
+    med = {k: {cn: float(np.median(v)) for cn, v in cs.items()} for k, cs in merged.items()}
+    probe = PROFILE_ROWS * 1000 * 4
+    cf = probe / (med["neg"]["FETCH_SIZE"] * 1024.0)
+    cw = probe / (med["neg"]["WRITE_SIZE"] * 1024.0)
+    simds, xcds = 1024, 8
+    lines = ["D=1000 workloads: per-kernel duration, HBM traffic and SQ counters (rocprofv3, five runs)", "",
+             "commands (repository root):",
+             "  rocprofv3 --kernel-trace --stats --output-format csv -d <T> -o run -- python -u bench.py --profile-d1000",
+             "  rocprofv3 --pmc FETCH_SIZE --output-format csv -d <F> -- python -u bench.py --profile-d1000",
+             "  rocprofv3 --pmc WRITE_SIZE --output-format csv -d <W> -- python -u bench.py --profile-d1000",
+             "  rocprofv3 --pmc SQ_WAVES SQ_BUSY_CYCLES SQ_WAVE_CYCLES SQ_INSTS_VALU SQ_INSTS_LDS SQ_INSTS_SALU "
+             "SQ_LDS_BANK_CONFLICT GRBM_GUI_ACTIVE --output-format csv -d <S1> -- python -u bench.py --profile-d1000",
+             "  rocprofv3 --pmc SQ_INSTS_MFMA SQ_VALU_MFMA_BUSY_CYCLES SQ_WAIT_ANY SQ_ACTIVE_INST_ANY SQ_INSTS_VMEM_RD "
+             "SQ_WAIT_INST_LDS GRBM_GUI_ACTIVE --output-format csv -d <S2> -- python -u bench.py --profile-d1000",
+             "  python bench.py --tiled-summary <T> <F> <W> <S1> <S2>", "",
+             f"Workload: the eight formulas on one 65536-row pass at D=1000 (default split mode), the hybrid and",
+             f"the composition at N=16384; 3 launches each.  Bytes: FETCH_SIZE/WRITE_SIZE (KiB per dispatch) scaled",
+             f"by the copy probe (torch.neg of {probe} bytes read and written): fetch x{cf:.3f}, write x{cw:.3f}.",
+             "Algorithmic bytes of the method per 65536-row pass: X read once, 262.1 MB, plus 0.26 MB written.",
+             "MFMA%: SQ_VALU_MFMA_BUSY_CYCLES / (1024 SIMDs x GRBM_GUI_ACTIVE/8).", "",
+             f"{'kernel':34s} {'calls':>5s} {'avg us':>8s} {'read MB':>8s} {'write MB':>9s} {'MFMA%':>6s} "
+             f"{'VALU/wave':>9s} {'LDS/wave':>8s} {'LDScf%':>6s} {'wait%':>6s}"]
+    for k in sorted(dur, key=lambda k: -dur[k][1]):
+        calls, tot = dur[k]
+        v = med.get(k, {})
+        cyc = v.get("GRBM_GUI_ACTIVE", 0.0) / xcds
+        waves = max(v.get("SQ_WAVES", 1.0), 1.0)
+        rd = v.get("FETCH_SIZE", float("nan")) * 1024 * cf / 1e6
+        wr = v.get("WRITE_SIZE", float("nan")) * 1024 * cw / 1e6
+        mf = 100 * v.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) / (simds * cyc) if cyc > 0 else float("nan")
+        lc = 100 * v.get("SQ_LDS_BANK_CONFLICT", 0.0) / 256 / cyc if cyc > 0 else float("nan")
+        wt = 100 * v.get("SQ_WAIT_ANY", 0.0) / max(v.get("SQ_WAVE_CYCLES", 1.0), 1.0)
+        lines.append(f"{k[:34]:34s} {calls:5d} {tot / calls / 1e3:8.2f} {rd:8.1f} {wr:9.1f} {mf:6.1f} "
+                     f"{v.get('SQ_INSTS_VALU', 0.0) / waves:9.0f} {v.get('SQ_INSTS_LDS', 0.0) / waves:8.0f} "
+                     f"{lc:6.1f} {wt:6.1f}")
+    with open(os.path.join(ROOT, "profiles", "tiled_d1000_kernels.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -427,10 +684,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="keep the built-in launch-shape heuristic")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--trace-summary", nargs=2, metavar=("HEADLINE_DIR", "SECONDARY_DIR"))
     ap.add_argument("--sq-summary", nargs=2, metavar=("P1_DIR", "P2_DIR"))
+    ap.add_argument("--profile-d1000", action="store_true", help="run only the D=1000 workloads (for rocprofv3)")
+    ap.add_argument("--tiled-summary", nargs=5, metavar=("TRACE", "FETCH", "WRITE", "SQ1", "SQ2"))
     args = ap.parse_args()
+    if args.tiled_summary:
+        tiled_summary(*args.tiled_summary)
+        return
     if args.pmc_summary:
         pmc_summary(*args.pmc_summary)
         return
@@ -451,6 +714,9 @@ def main():
     from paper_1407_7737_amd.inputs import population
 
     assert torch.cuda.is_available(), "bench needs a GPU"
+    if args.profile_d1000:
+        profile_d1000(torch, c)
+        return
     dev = torch.device("cuda:0")
     x32h = population(N, DIM, seed=0, dtype=np.float32)
     x32 = torch.from_numpy(x32h).to(dev)
@@ -459,6 +725,14 @@ def main():
     outs64 = {fid: torch.empty(N, dtype=torch.float64, device=dev) for fid in FIDS}
     c.initialize(DIM, N, 0)
     stream = torch.cuda.current_stream()
+    # launch shapes from the autotuner (every candidate timed on the bench's own buffers; the
+    # search log goes into the result line)
+    tuning = {}
+    if not args.no_tune:
+        for fid in FIDS:
+            t = c.tune(fid, x32, fp64=False, reps=5)
+            t64 = c.tune(fid, x64, fp64=True, reps=3)
+            tuning[NAMES[fid]] = {"split": t, "fp64": t64}
 
     def step(fp64: bool, events=None):
         for fid in FIDS:
@@ -495,6 +769,11 @@ def main():
 
     wall32, per32 = timed(False)
     wall64, per64 = timed(True)
+    # the plain FP32 mode (FP32 matrix products) on the same points, per formula
+    c.set_mode(c.MODE_FP32)
+    plain32 = {fid: event_time_ms(torch, lambda: c.func_evaluatef(fid, x32, out=outs32[fid]), 10) for fid in FIDS}
+    c.set_mode(c.MODE_SPLIT)
+    torch.cuda.synchronize()
     # measured peaks beside the nominal ones: streaming reads of the FP32 population, and the
     # dense BF16 matrix-core rate
     meas = {"hbm_read_gbs": c.probe_read_gbs(x32), "mfma_bf16_tflops": c.probe_mfma_bf16_tflops(),
@@ -520,9 +799,12 @@ def main():
     ach = bytes32 / (per32[dom] * 1e-3) / 1e9
     traffic = measured_traffic(dom)
     per_fn = {NAMES[f]: {"split_ms": round(per32[f], 5), "fp64_ms": round(per64[f], 5),
+                         "fp32_plain_ms": round(plain32[f], 5),
                          "split_evals_per_s": N / (per32[f] * 1e-3), "fp64_evals_per_s": N / (per64[f] * 1e-3),
+                         "fp32_plain_evals_per_s": N / (plain32[f] * 1e-3),
                          "split_hbm_frac": bytes32 / (per32[f] * 1e-3) / 1e9 / HBM_PEAK_GBS,
                          "fp64_hbm_frac": bytes64 / (per64[f] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "fp32_plain_hbm_frac": bytes32 / (plain32[f] * 1e-3) / 1e9 / HBM_PEAK_GBS,
                          "kernel": resident_key(f)} for f in FIDS}
     res = {
         "metric": "evals/sec at D=100,N=2^18: split-BF16 MFMA vs FP64 path; % of roofline",
@@ -549,6 +831,8 @@ def main():
         "fp64_path": {"value": evals * args.steps / wall64, "unit": "evals/s", "ms_per_step": ms64,
                       "split_over_fp64": (evals * args.steps / wall32) / (evals * args.steps / wall64)},
         "per_function": per_fn,
+        "autotune": tuning,
+        "paper_context": PAPER_CONTEXT,
     }
     if not args.no_secondary:
         res["secondary"] = secondary(torch, c)

@@ -205,6 +205,31 @@ int curob_generate_composition(int fid, int dim, unsigned long long seed, double
 int curob_de_run(int fid, int fp64, int np, double F, double CR, unsigned long long seed, void *d_pop, void *d_fit,
                  void *d_trial, void *d_ftrial, unsigned long long *d_gen, int generations);
 
+/* ---- autotuned launch shapes of the single-call kernel ------------------------------------
+ * Basic functions up to 128 dimensions run on one persistent kernel whose launch shape -- waves
+ * (16-row column blocks) per workgroup and workgroups per 8 CUs -- is chosen per key (path,
+ * D bucket, formula class, row-count bucket): D buckets 0..4 for dim <= 16, 32, 64, 96, 128;
+ * the class is 2 * (formula family) + rotated; the row bucket is floor(log2 n) in 4..24; the
+ * path is that of func_evaluate (fp64 != 0) or of func_evaluatef in the current mode.  Keys
+ * without an entry use the built-in heuristic (as many waves as the LDS holds, at most
+ * occupancy x CUs workgroups).  Entries live until dispose.
+ *
+ * curob_shape_key: the four key values for function fid, path and n rows (CUROB_E_ARG when the
+ *   function does not run on that kernel, i.e. dim > 128, hybrids, compositions).
+ * curob_set_shape: installs (waves 1..16, grid_per8 >= 0; 0 = occupancy x CUs) for a key, e.g.
+ *   from a cache of earlier tuning; waves = 0 removes the key's entry.  Waves are clamped to what
+ *   the LDS allows for the problem at launch.
+ * curob_tune: times every candidate (waves {1, 2, 4, 6, 8, 12, 16} up to the LDS limit x
+ *   grid_per8 {0, 4, 8, 12, 16, 24, 32}) with `reps` launches each (after one warm-up) on the
+ *   caller's device buffers d_x (n rows) and d_out, on the library stream (waits for it), and
+ *   installs the fastest for the key of (fid, path, n).  Outputs: the best shape and its time
+ *   per launch in microseconds; if log != NULL, up to log_cap triples (waves, grid_per8, us), one
+ *   per candidate timed, and their count in *log_len.  d_out is overwritten. */
+int curob_shape_key(int fid, int fp64, int n, int *key4);
+int curob_set_shape(const int *key4, int waves, int grid_per8);
+int curob_tune(int fid, int fp64, const void *d_x, int n, void *d_out, int reps, int *best_waves, int *best_grid_per8,
+               float *best_us, float *log, int log_cap, int *log_len);
+
 /* ---- batched populations (one persistent launch, replayed as a HIP graph) --------------- */
 
 typedef struct curob_batch curob_batch;

@@ -30,7 +30,7 @@ __all__ = [
     "initialize", "dispose", "func_evaluate", "func_evaluatef", "h_func_evaluate", "h_func_evaluatef",
     "set_stream", "set_mode", "define_basic", "define_hybrid", "define_composition", "get_problem",
     "generate_basic", "get_dim", "get_structure", "get_composition", "generate_structure",
-    "generate_composition", "last_error", "CurobError", "Batch", "DE",
+    "generate_composition", "last_error", "CurobError", "Batch", "DE", "tune", "shape_key",
 ]
 
 # dimension given to initialize, for the shape checks of the device calls (None: not initialised
@@ -262,6 +262,62 @@ def probe_mfma_bf16_tflops(reps: int = 5) -> float:
     tf = ctypes.c_double()
     check(lib.curob_probe_mfma_bf16(int(reps), ctypes.byref(tf)))
     return tf.value
+
+
+def _arch() -> str:
+    import torch
+    prop = torch.cuda.get_device_properties(torch.cuda.current_device())
+    return f"{getattr(prop, 'gcnArchName', 'gpu')}|{prop.name}|{prop.multi_processor_count}cu"
+
+
+def shape_key(fid: int, n: int, fp64: bool = False) -> str:
+    """Cache key of the launch shape of fid on n rows: architecture, path, D bucket, formula
+    class and row bucket (curob_shape_key)."""
+    k = (ctypes.c_int * 4)()
+    check(lib.curob_shape_key(int(fid), int(bool(fp64)), int(n), k))
+    return f"{_arch()}|path{k[0]}|d{k[1]}|class{k[2]}|n{k[3]}"
+
+
+def tune(fid: int, x, fp64: bool = False, reps: int = 10, cache: str | None = None) -> dict:
+    """Autotunes the single-call launch shape of fid for x's row count (curob_tune) on x and a
+    scratch output, or applies the entry of the JSON cache for the same key.  Returns the chosen
+    shape with its time and, when freshly tuned, the search log (one entry per candidate)."""
+    import json
+
+    import torch
+    key = shape_key(fid, x.shape[0], fp64)
+    k4 = (ctypes.c_int * 4)()
+    check(lib.curob_shape_key(int(fid), int(bool(fp64)), int(x.shape[0]), k4))
+    entries = {}
+    if cache and os.path.exists(cache):
+        with open(cache) as f:
+            entries = json.load(f)
+        if key in entries:
+            e = entries[key]
+            check(lib.curob_set_shape(k4, int(e["waves"]), int(e["grid_per8"])))
+            return dict(e, key=key, cached=True)
+    want = torch.float64 if fp64 else torch.float32
+    if not (x.is_cuda and x.dtype == want and x.is_contiguous() and x.dim() == 2 and x.shape[1] == _current_dim()):
+        raise ValueError(f"x must be a contiguous (n, dim) {want} CUDA tensor")
+    out = torch.empty(x.shape[0], dtype=want, device=x.device)
+    bw, bg = ctypes.c_int(), ctypes.c_int()
+    bus = ctypes.c_float()
+    cap = 64
+    log = (ctypes.c_float * (3 * cap))()
+    nlog = ctypes.c_int()
+    check(lib.curob_set_stream(_torch_stream()))
+    check(lib.curob_tune(int(fid), int(bool(fp64)), _ptr(x), int(x.shape[0]), _ptr(out), int(reps), ctypes.byref(bw),
+                         ctypes.byref(bg), ctypes.byref(bus), log, cap, ctypes.byref(nlog)))
+    res = {"waves": bw.value, "grid_per8": bg.value, "us": round(float(bus.value), 3)}
+    if cache:
+        entries[key] = res
+        tmp = cache + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(entries, f, indent=1, sort_keys=True)
+        os.replace(tmp, cache)
+    search = [{"waves": int(log[3 * i]), "grid_per8": int(log[3 * i + 1]), "us": round(float(log[3 * i + 2]), 3)}
+              for i in range(nlog.value)]
+    return dict(res, key=key, cached=False, search=search)
 
 
 class DE:

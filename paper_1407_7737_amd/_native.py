@@ -34,7 +34,7 @@ EXPORTED = [
     "curob_batch_configure", "curob_batch_shape", "curob_batch_tune", "curob_batch_destroy",
     "curob_probe_read", "curob_probe_mfma_bf16", "curob_get_dim", "curob_get_info", "curob_get_structure",
     "curob_get_composition", "curob_generate_info", "curob_generate_structure", "curob_generate_composition",
-    "func_evaluatef_noalloc", "curob_de_run",
+    "func_evaluatef_noalloc", "curob_de_run", "curob_shape_key", "curob_set_shape", "curob_tune",
 ]
 BATCH_KEY_BASE = 2048  # population i of a batch keys its random data like custom id 2048 + i
 
@@ -57,6 +57,10 @@ def _load():
         "func_evaluate": (i32, [i32, vp, i32, vp]),
         "func_evaluatef": (i32, [i32, vp, i32, vp]),
         "func_evaluatef_noalloc": (i32, [i32, vp, i32, vp]),
+        "curob_shape_key": (i32, [i32, i32, i32, ip]),
+        "curob_set_shape": (i32, [ip, i32, i32]),
+        "curob_tune": (i32, [i32, i32, vp, i32, vp, i32, ip, ip, ctypes.POINTER(ctypes.c_float),
+                             ctypes.POINTER(ctypes.c_float), i32, ip]),
         "curob_de_run": (i32, [i32, i32, i32, ctypes.c_double, ctypes.c_double, u64, vp, vp, vp, vp, vp, i32]),
         "h_func_evaluate": (i32, [i32, vp, i32, vp]),
         "h_func_evaluatef": (i32, [i32, vp, i32, vp]),

@@ -84,6 +84,7 @@ int hip_fail(hipError_t e, const char *what) {
 }
 
 void free_context() {
+  clear_shape_overrides();
   g_ctx.entries.clear();
   g_ctx.scratch.release();
   if (g_ctx.stage_x) (void)hipFree(g_ctx.stage_x);
@@ -424,6 +425,93 @@ int curob_de_run(int fid, int fp64, int np, double F, double CR, unsigned long l
     he = launch_de_select(fp64 != 0, d_pop, d_fit, d_trial, d_ftrial, np, g_ctx.dim, d_gen, g_ctx.stream);
     if (he != hipSuccess) return hip_fail(he, "selection");
   }
+  return CUROB_OK;
+}
+
+int curob_shape_key(int fid, int fp64, int n, int *key4) {
+  Entry *e = nullptr;
+  int rc = check_eval_args(fid, nullptr, 0, nullptr, &e);
+  if (rc != CUROB_OK) return rc;
+  const int path = fp64 ? PATH_F64 : fp32_path(fid);
+  if (!(e->host.type == Problem::BASIC && e->dev[path].ready))
+    return fail(CUROB_E_ARG, "function id %d does not run on the resident kernel (dimension <= 128)", fid);
+  if (!key4) return fail(CUROB_E_ARG, "null pointer");
+  const ShapeKey k = shape_key(path, e->dev[path].pb, n < 1 ? 1 : n);
+  key4[0] = k.path;
+  key4[1] = k.dbucket;
+  key4[2] = k.fclass;
+  key4[3] = k.nbucket;
+  return CUROB_OK;
+}
+
+int curob_set_shape(const int *key4, int waves, int grid_per8) {
+  int rc = check_ready();
+  if (rc != CUROB_OK) return rc;
+  if (!key4) return fail(CUROB_E_ARG, "null pointer");
+  if (waves < 0 || waves > 16 || grid_per8 < 0) return fail(CUROB_E_ARG, "waves must be in 0..16, grid_per8 >= 0");
+  ShapeKey k{key4[0], key4[1], key4[2], key4[3]};
+  if (waves == 0) {
+    erase_shape_override(k);  // back to the built-in heuristic
+    return CUROB_OK;
+  }
+  set_shape_override(k, waves, grid_per8);
+  return CUROB_OK;
+}
+
+int curob_tune(int fid, int fp64, const void *d_x, int n, void *d_out, int reps, int *best_waves, int *best_grid_per8,
+               float *best_us, float *log, int log_cap, int *log_len) {
+  Entry *e = nullptr;
+  int rc = check_eval_args(fid, d_x, n, d_out, &e);
+  if (rc != CUROB_OK) return rc;
+  if (n < 1 || reps < 1) return fail(CUROB_E_ARG, "tuning needs n >= 1 and reps >= 1");
+  const int path = fp64 ? PATH_F64 : fp32_path(fid);
+  if (!(e->host.type == Problem::BASIC && e->dev[path].ready))
+    return fail(CUROB_E_ARG, "function id %d does not run on the resident kernel (dimension <= 128)", fid);
+  const DevProb &pb = e->dev[path].pb;
+  const int wmax = resident_max_waves(path, pb);
+  static const int kWaves[] = {1, 2, 4, 6, 8, 12, 16};
+  static const int kGrid[] = {0, 4, 8, 12, 16, 24, 32};
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  hipError_t he = hipEventCreate(&t0);
+  if (he == hipSuccess) he = hipEventCreate(&t1);
+  if (he != hipSuccess) return hip_fail(he, "creating timing events");
+  float best = 3.0e38f;
+  int bw = 0, bg = 0, nlog = 0;
+  for (int w : kWaves) {
+    if (w > wmax) continue;
+    for (int g : kGrid) {
+      const LaunchShape ls = resident_shape_for(path, pb, n, g_ctx.num_cu, w, g);
+      he = launch_resident(path, pb, d_x, d_out, n, ls, g_ctx.stream);  // warm-up
+      if (he == hipSuccess) he = hipEventRecord(t0, g_ctx.stream);
+      for (int r = 0; r < reps && he == hipSuccess; ++r) he = launch_resident(path, pb, d_x, d_out, n, ls, g_ctx.stream);
+      if (he == hipSuccess) he = hipEventRecord(t1, g_ctx.stream);
+      if (he == hipSuccess) he = hipEventSynchronize(t1);
+      float ms = 0.0f;
+      if (he == hipSuccess) he = hipEventElapsedTime(&ms, t0, t1);
+      if (he != hipSuccess) break;
+      const float us = 1000.0f * ms / static_cast<float>(reps);
+      if (log && nlog < log_cap) {
+        log[3 * nlog] = static_cast<float>(ls.waves);
+        log[3 * nlog + 1] = static_cast<float>(g);
+        log[3 * nlog + 2] = us;
+        ++nlog;
+      }
+      if (us < best) {
+        best = us;
+        bw = ls.waves;
+        bg = g;
+      }
+    }
+    if (he != hipSuccess) break;
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  if (he != hipSuccess) return hip_fail(he, "timing a candidate shape");
+  set_shape_override(shape_key(path, pb, n), bw, bg);
+  if (best_waves) *best_waves = bw;
+  if (best_grid_per8) *best_grid_per8 = bg;
+  if (best_us) *best_us = best;
+  if (log_len) *log_len = nlog;
   return CUROB_OK;
 }
 

@@ -88,6 +88,23 @@ struct LaunchShape {
 };
 LaunchShape resident_shape(int path, const DevProb &pb, int n, int num_cu);
 
+// Autotuned launch shapes.  A key is (path, D bucket, formula class, row-count bucket): D
+// buckets 0..4 for D <= 16, 32, 64, 96, 128; the class is 2 * kind + rotated; the row bucket is
+// floor(log2 n) clamped to 4..24.  An entry fixes the waves per workgroup and the workgroups
+// per 8 CUs of the resident kernel (clamped to what the LDS and the occupancy allow).
+struct ShapeKey {
+  int path, dbucket, fclass, nbucket;
+};
+ShapeKey shape_key(int path, const DevProb &pb, int n);
+void set_shape_override(const ShapeKey &k, int waves, int grid_per8);
+void clear_shape_overrides();
+void erase_shape_override(const ShapeKey &k);
+bool get_shape_override(const ShapeKey &k, int *waves, int *grid_per8);
+// Largest waves per workgroup the LDS and the path allow for this problem.
+int resident_max_waves(int path, const DevProb &pb);
+// The shape for an explicit (waves, workgroups per 8 CUs), clamped like an override.
+LaunchShape resident_shape_for(int path, const DevProb &pb, int n, int num_cu, int waves, int grid_per8);
+
 // Resident kernel (dimension <= 128): evaluates n rows of x (device, row-major) into out.
 hipError_t launch_resident(int path, const DevProb &pb, const void *x, void *out, int n, const LaunchShape &ls,
                            hipStream_t st);
