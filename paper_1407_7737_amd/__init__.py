@@ -419,19 +419,18 @@ class Batch:
         return dict(zip(("waves", "groups_per_item", "grid", "items"), (a.value for a in v)))
 
     def signature(self) -> str:
-        import hashlib
-
-        import torch
-        h = hashlib.sha256()
-        for a in (self.fids, self.dims, self.counts):
-            h.update(a.tobytes())
-        h.update(torch.cuda.get_device_name().encode())
-        return h.hexdigest()[:24]
+        """Tuning-cache key: architecture, path (the split path), the largest dimension's bucket
+        (<= 16, 32, 64, 96, 128), and log2 buckets of the total row count and of the number of
+        populations -- batches alike in these share a launch shape."""
+        dmax = int(self.dims.max()) if self.k else 0
+        dbucket = 0 if dmax <= 16 else 1 if dmax <= 32 else 2 if dmax <= 64 else 3 if dmax <= 96 else 4
+        rows = max(1, int(self.counts.sum()))
+        return f"{_arch()}|batch-split|d{dbucket}|rows{rows.bit_length() - 1}|pops{max(1, self.k).bit_length() - 1}"
 
     def tune(self, reps: int = 20, cache: str | None = None) -> dict:
         """Autotunes the launch shape on the bound buffers (curob_batch_tune).  With a cache
-        path (JSON), a shape stored for the same populations and device is applied without
-        timing, and a freshly tuned one is stored."""
+        path (JSON), a shape stored under the same key (signature()) is applied without timing,
+        and a freshly tuned one is stored."""
         import json
         key = self.signature()
         entries = {}

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 
+#include "eval_rowres.h"
 #include "kernels.h"
 
 namespace curob {
@@ -14,6 +15,8 @@ hipError_t launch_tiled_split6(int, const TiledProb &, const void *, void *, int
                                hipStream_t);
 hipError_t launch_tiled_f32(int, const TiledProb &, const void *, void *, int, int, void *, void *, void *, hipStream_t);
 hipError_t launch_tiled_f64(int, const TiledProb &, const void *, void *, int, int, void *, void *, void *, hipStream_t);
+hipError_t launch_rowres_split(int, const TiledProb &, const void *, void *, int, int, hipStream_t);
+hipError_t launch_rowres_split6(int, const TiledProb &, const void *, void *, int, int, hipStream_t);
 hipError_t launch_blend(bool f64, const void *x, int n, int D, int nc, const double *o, const double *sigma,
                         const double *lambda, const double *bias, const void *G, int gstride, double fopt, void *out,
                         hipStream_t st);
@@ -25,6 +28,21 @@ hipError_t launch_tiled(int path, int kind_hint, const TiledProb &tp, const void
     case PATH_SPLIT6: return launch_tiled_split6(kind_hint, tp, x, out, n, cap, partials, zbuf, pack, st);
     case PATH_F32: return launch_tiled_f32(kind_hint, tp, x, out, n, cap, partials, zbuf, pack, st);
     case PATH_F64: return launch_tiled_f64(kind_hint, tp, x, out, n, cap, partials, zbuf, pack, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+bool rowres_fits(const TiledProb &tp, int path) {
+  if (!is_split(path) || tp.rowwise || tp.goff == nullptr || tp.D * 4 >= 65536) return false;
+  const int CB = tp.any_pairwise ? 1 : 2;
+  return rowres::carve(tp.Dp, tp.S, CB, CB == 1).total <= kMaxLdsBytes;
+}
+
+hipError_t launch_rowres(int path, int kind_hint, const TiledProb &tp, const void *x, void *out, int n, int num_cu,
+                         hipStream_t st) {
+  switch (path) {
+    case PATH_SPLIT: return launch_rowres_split(kind_hint, tp, x, out, n, num_cu, st);
+    case PATH_SPLIT6: return launch_rowres_split6(kind_hint, tp, x, out, n, num_cu, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -112,6 +130,7 @@ hipError_t build_composite(const Problem &p, CompositeDev &cd, std::string &err)
     std::copy(c.o.begin(), c.o.end(), o.begin() + static_cast<size_t>(i) * p.dim);
     CompositeDev::Component &cc = cd.comps[i];
     cc.six = problem_needs_six(c);
+    cc.hybrid = c.type == Problem::HYBRID;
     if (fits_resident(c)) {
       cc.resident = true;
       for (int path = 0; path < PATH_COUNT; ++path) {
@@ -191,6 +210,10 @@ hipError_t launch_composite(int path, bool split_auto, const CompositeDev &cd, c
                             int num_cu, CompositeScratch &sc, hipStream_t st) {
   if (!cd.ready) return hipErrorNotSupported;
   const size_t esz = path == PATH_F64 ? 8 : 4;
+  // basic functions and hybrids the row-resident kernel takes: one launch over all rows, no
+  // scratch
+  if (!cd.is_composition && rowres_fits(cd.tiled[path].tp, path))
+    return launch_rowres(path, cd.kind_hint, cd.tiled[path].tp, x, out, n, num_cu, st);
   const int cap = sc.cap;
   if (cap < kTileRows || cap % kTileRows != 0) return hipErrorInvalidValue;
   for (int c0 = 0; c0 < n; c0 += cap) {
@@ -213,8 +236,10 @@ hipError_t launch_composite(int path, bool split_auto, const CompositeDev &cd, c
         const DevProb &pb = cc.res[cp].pb;
         e = launch_resident(cp, pb, xc, gi, ch, resident_shape(cp, pb, ch, num_cu), st);
       } else {
-        const int hint = cc.tiled[cp].tp.nsegs == 1 ? cc.tiled[cp].tp.segs[0].kind : -1;
-        e = launch_tiled(cp, hint, cc.tiled[cp].tp, xc, gi, ch, cap, sc.partials, sc.zbuf, sc.pack, st);
+        const TiledProb &ctp = cc.tiled[cp].tp;
+        const int hint = ctp.nsegs == 1 && !cc.hybrid ? ctp.segs[0].kind : -1;
+        if (rowres_fits(ctp, cp)) e = launch_rowres(cp, hint, ctp, xc, gi, ch, num_cu, st);
+        else e = launch_tiled(cp, hint, ctp, xc, gi, ch, cap, sc.partials, sc.zbuf, sc.pack, st);
       }
       if (e != hipSuccess) return e;
     }

@@ -20,6 +20,7 @@ struct CompositeDev {
     DevTables res[PATH_COUNT];
     bool resident = false;
     bool six = false;  // split mode: six products
+    bool hybrid = false;
   };
   bool ready = false;
   bool is_composition = false;

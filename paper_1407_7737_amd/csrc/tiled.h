@@ -10,6 +10,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
 #include <string>
 #include <vector>
 
@@ -54,6 +55,11 @@ struct TiledProb {
   const void *qfrag;    // dense tiles of s*Q per block, MFMA A-operand order
   const int4 *blocks;   // per block: padded offset, padded size, first tile, k-tiles
   const int4 *groups;   // per output group: block, first m-tile, m-tile count, segment
+  // row-resident kernel (split paths): per padded position the byte offset of its variable in
+  // an LDS row (padding: the zero slot at column D) and o_hi in packed order (0 for padding)
+  const uint16_t *goff;
+  const float *ohp;
+  int S;          // LDS row stride (floats) of the row-resident kernel
   int D, Dp, nblocks, ngroups, nsegs;
   int any_pairwise;
   int rowwise;    // unrotated basic problem: z = s (x - o) + c' per variable, no MFMA work
@@ -77,6 +83,13 @@ hipError_t build_tiled(const Problem &p, int path, TiledDev &td, std::string &er
 size_t tiled_partials_bytes(const TiledProb &tp, int path, int rows);
 size_t tiled_z_bytes(const TiledProb &tp, int path, int rows);
 size_t tiled_pack_bytes(const TiledProb &tp, int path, int rows);
+
+// Whether the row-resident kernel takes this problem on this path (split paths, rotated, the
+// rows and tables fit the LDS); it needs no scratch.
+bool rowres_fits(const TiledProb &tp, int path);
+// Evaluates rows [0, n) of x into out with the row-resident kernel (any n).
+hipError_t launch_rowres(int path, int kind_hint, const TiledProb &tp, const void *x, void *out, int n, int num_cu,
+                         hipStream_t st);
 
 // Evaluates rows [0, n) of x into out using scratch buffers sized for cap rows (n <= cap, cap a
 // multiple of kTileRows).

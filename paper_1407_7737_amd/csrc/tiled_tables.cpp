@@ -187,6 +187,18 @@ hipError_t build_tiled(const Problem &p, int path, TiledDev &td, std::string &er
 
   TiledProb &tp = td.tp;
   tp = TiledProb{};
+  // row-resident kernel tables (split paths): byte offset of each padded position's variable
+  // within an LDS row, the zero slot at column D for padding, and o_hi in packed order
+  std::vector<uint16_t> goff16(Dp, static_cast<uint16_t>(D * 4));
+  std::vector<float> ohp(Dp, 0.0f);
+  if (!f64 && D * 4 < 65536) {
+    for (int pp = 0; pp < Dp; ++pp)
+      if (gidx[pp] >= 0) {
+        goff16[pp] = static_cast<uint16_t>(gidx[pp] * 4);
+        ohp[pp] = static_cast<float>(p.o[gidx[pp]]);
+      }
+  }
+  tp.S = lds_stride(D, 0);
   tp.D = D;
   tp.Dp = Dp;
   tp.nblocks = static_cast<int>(blocks.size());
@@ -252,6 +264,8 @@ hipError_t build_tiled(const Problem &p, int path, TiledDev &td, std::string &er
   if ((e = up(qfrag.data(), qfrag.size(), &tp.qfrag)) != hipSuccess) return e;
   if ((e = up(blk4.data(), blk4.size() * 4, reinterpret_cast<const void **>(&tp.blocks))) != hipSuccess) return e;
   if ((e = up(grp4.data(), grp4.size() * 4, reinterpret_cast<const void **>(&tp.groups))) != hipSuccess) return e;
+  if ((e = up(goff16.data(), goff16.size() * 2, reinterpret_cast<const void **>(&tp.goff))) != hipSuccess) return e;
+  if ((e = up(ohp.data(), ohp.size() * 4, reinterpret_cast<const void **>(&tp.ohp))) != hipSuccess) return e;
   td.ready = true;
   return hipSuccess;
 }
