@@ -17,6 +17,9 @@ hipError_t launch_tiled_f32(int, const TiledProb &, const void *, void *, int, i
 hipError_t launch_tiled_f64(int, const TiledProb &, const void *, void *, int, int, void *, void *, void *, hipStream_t);
 hipError_t launch_rowres_split(int, const TiledProb &, const void *, void *, int, int, hipStream_t);
 hipError_t launch_rowres_split6(int, const TiledProb &, const void *, void *, int, int, hipStream_t);
+hipError_t launch_rowres_comp(const void *desc, int nc, int Dpmax, int S, int CB, const float *x, int n, int D,
+                              const double *o64, const double *sig, const double *lam, const double *cb, double fopt,
+                              float *out, int num_cu, hipStream_t st);
 hipError_t launch_blend(bool f64, const void *x, int n, int D, int nc, const double *o, const double *sigma,
                         const double *lambda, const double *bias, const void *G, int gstride, double fopt, void *out,
                         hipStream_t st);
@@ -157,6 +160,49 @@ hipError_t build_composite(const Problem &p, CompositeDev &cd, std::string &err)
   if ((e = up(p.sigma, &cd.sig)) != hipSuccess) return e;
   if ((e = up(p.lambda, &cd.lam)) != hipSuccess) return e;
   if ((e = up(p.cbias, &cd.cb)) != hipSuccess) return e;
+  // the fused composition kernel: every component above the resident range, rotated ones on the
+  // row-resident kernel, unrotated ones without pair terms
+  bool fused = p.dim * 4 < 65536;
+  int dpmax = 0, cbn = 2;
+  for (const auto &cc : cd.comps) {
+    if (cc.resident) {
+      fused = false;
+      break;
+    }
+    for (int path : {PATH_SPLIT, PATH_SPLIT6}) {
+      const TiledProb &tp = cc.tiled[path].tp;
+      if (tp.rowwise) {
+        if (tp.any_pairwise) fused = false;
+      } else {
+        if (!rowres_fits(tp, path)) fused = false;
+        dpmax = std::max(dpmax, tp.Dp);
+        if (tp.any_pairwise) cbn = 1;
+      }
+    }
+  }
+  if (fused && rowres::comp_carve(dpmax, lds_stride(p.dim, 0), cbn).total <= kMaxLdsBytes) {
+    for (int mode = 0; mode < 3; ++mode) {
+      std::vector<rowres::CompDesc> desc(cd.comps.size());
+      for (size_t i = 0; i < cd.comps.size(); ++i) {
+        const auto &cc = cd.comps[i];
+        const bool six = mode == 0 ? cc.six : mode == 2;
+        const TiledProb &tp = cc.tiled[six ? PATH_SPLIT6 : PATH_SPLIT].tp;
+        desc[i].tp = tp;
+        desc[i].six = six ? 1 : 0;
+        desc[i].unrotated = tp.rowwise;
+      }
+      void *d = nullptr;
+      if ((e = hipMalloc(&d, desc.size() * sizeof(rowres::CompDesc))) != hipSuccess) return e;
+      cd.allocs.push_back(d);
+      if ((e = hipMemcpy(d, desc.data(), desc.size() * sizeof(rowres::CompDesc), hipMemcpyHostToDevice)) != hipSuccess)
+        return e;
+      cd.rr_desc[mode] = d;
+    }
+    cd.rr_ok = true;
+    cd.rr_dpmax = dpmax;
+    cd.rr_S = lds_stride(p.dim, 0);
+    cd.rr_cb = cbn;
+  }
   cd.ready = true;
   return hipSuccess;
 }
@@ -214,6 +260,13 @@ hipError_t launch_composite(int path, bool split_auto, const CompositeDev &cd, c
   // scratch
   if (!cd.is_composition && rowres_fits(cd.tiled[path].tp, path))
     return launch_rowres(path, cd.kind_hint, cd.tiled[path].tp, x, out, n, num_cu, st);
+  // compositions with every component on the row-resident kernel: one fused launch
+  if (cd.is_composition && cd.rr_ok && is_split(path)) {
+    const int mode = split_auto ? 0 : (path == PATH_SPLIT6 ? 2 : 1);
+    return launch_rowres_comp(cd.rr_desc[mode], static_cast<int>(cd.comps.size()), cd.rr_dpmax, cd.rr_S, cd.rr_cb,
+                              static_cast<const float *>(x), n, cd.dim, cd.o64, cd.sig, cd.lam, cd.cb, cd.fopt,
+                              static_cast<float *>(out), num_cu, st);
+  }
   const int cap = sc.cap;
   if (cap < kTileRows || cap % kTileRows != 0) return hipErrorInvalidValue;
   for (int c0 = 0; c0 < n; c0 += cap) {

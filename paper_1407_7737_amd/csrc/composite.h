@@ -32,6 +32,11 @@ struct CompositeDev {
   const double *o64 = nullptr; // component optima, ncomp x dim
   const double *sig = nullptr, *lam = nullptr, *cb = nullptr;
   double fopt = 100.0;
+  // fused composition on the split paths (every component on the same staged rows): component
+  // descriptors per split mode (0: three or six products per component, 1: three, 2: six)
+  bool rr_ok = false;
+  const void *rr_desc[3] = {nullptr, nullptr, nullptr};
+  int rr_dpmax = 0, rr_S = 0, rr_cb = 2;
   void release();
 };
 

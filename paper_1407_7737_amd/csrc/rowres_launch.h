@@ -43,6 +43,31 @@ hipError_t launch_path(int kind_hint, const TiledProb &tp, const void *x, void *
   return hipLaunchKernel(fn, dim3(grid > 0 ? grid : 1), dim3(kThreads), args, static_cast<size_t>(L.total), st);
 }
 
+// Fused composition: one launch over all rows (desc: device array of nc CompDesc).
+inline hipError_t launch_comp(const void *desc, int nc, int Dpmax, int S, int CB, const float *x, int n, int D,
+                              const double *o64, const double *sig, const double *lam, const double *cb, double fopt,
+                              float *out, int num_cu, hipStream_t st) {
+  const void *fn = CB == 1 ? reinterpret_cast<const void *>(&k_rowres_comp<1>)
+                           : reinterpret_cast<const void *>(&k_rowres_comp<2>);
+  const CompCarve L = comp_carve(Dpmax, S, CB);
+  if (L.total > kMaxLdsBytes) return hipErrorInvalidValue;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, L.total);
+  if (e != hipSuccess) return e;
+  const int R = 16 * CB;
+  const int tiles = (n + R - 1) / R;
+  const int per_cu = kMaxLdsBytes / L.total > 0 ? kMaxLdsBytes / L.total : 1;
+  const int cap = num_cu * per_cu;
+  const int grid = tiles < cap ? tiles : cap;
+  int wide = (D % 4 == 0 && (reinterpret_cast<uintptr_t>(x) % 16) == 0) ? 1 : 0;
+  const CompDesc *da = static_cast<const CompDesc *>(desc);
+  int nca = nc, dpa = Dpmax, sa = S, na = n, dd = D;
+  const float *xa = x;
+  float *oa = out;
+  double fo = fopt;
+  void *args[] = {&da, &nca, &dpa, &sa, &xa, &na, &dd, &o64, &sig, &lam, &cb, &fo, &oa, &wide};
+  return hipLaunchKernel(fn, dim3(grid > 0 ? grid : 1), dim3(kThreads), args, static_cast<size_t>(L.total), st);
+}
+
 }  // namespace rowres
 
 }  // namespace curob
