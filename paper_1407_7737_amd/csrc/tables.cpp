@@ -211,7 +211,7 @@ bool build_host_tables(const Problem &p, int path, HostTables &ht, std::string &
     }
     store(ht.cz, pp, c - corr + (kind == K_SCHWEFEL ? 420.9687462275036 : 0.0));
     double cf = formula_coef(base, i, D);
-    if (kind == K_GRIEWANK && !f64) cf /= 2.0 * M_PI;  // FP32 cosine takes revolutions
+    if (kind == K_GRIEWANK) cf /= 2.0 * M_PI;  // the cosine takes revolutions
     store(ht.coef, pp, cf);
     if (pair) {
       const int ni = i + 1 < D ? i + 1 : (wraps ? 0 : -1);

@@ -120,7 +120,7 @@ hipError_t build_tiled(const Problem &p, int path, TiledDev &td, std::string &er
       store(cz, pp, sg.c - B.s * corr + (kind == K_SCHWEFEL ? 420.9687462275036 : 0.0));
       const int n_f = hybrid ? sg.n : D;
       double cf = formula_coef(sg.base, idx_in_seg[pp], n_f);
-      if (kind == K_GRIEWANK && !f64) cf /= 2.0 * M_PI;
+      if (kind == K_GRIEWANK) cf /= 2.0 * M_PI;  // the cosine takes revolutions
       store(coef, pp, cf);
       if (kind_is_pairwise(kind)) {
         const bool wraps = kind_pair_wraps(kind);
