@@ -187,7 +187,7 @@ SIX = {3, 7, 8, 12, 13, 16, 17}
 
 
 def products(base: int, n: int) -> int:
-    return 6 if base in SIX or (base == 14 and n < 10) or (base == 2 and n < 50) else 3
+    return 6 if base in SIX or (base in (4, 14) and n < 10) or (base == 2 and n < 50) else 3
 
 
 def rotation_work(c, pid: int, comp: int = -1):

@@ -780,13 +780,13 @@ __device__ __forceinline__ void resident_eval(const DevProb &pb, const typename 
       if constexpr (DIRECT) {
         T s[3];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) s[k] = a[b].get(k) - T(pb.padc[k]);
+        for (int k = 0; k < 3; ++k) s[k] = a[b].get_minus(k, pb.padc[k]);
         pend = finalize<KIND, T>(s, a[b].p, pb.Df) + T(pb.bias);
         prow = row;
       } else if (q == 0 && row < n) {
         T s[3];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) s[k] = a[b].get(k) - T(pb.padc[k]);
+        for (int k = 0; k < 3; ++k) s[k] = a[b].get_minus(k, pb.padc[k]);
         out[row] = finalize<KIND, T>(s, a[b].p, pb.Df) + T(pb.bias);
       }
     }

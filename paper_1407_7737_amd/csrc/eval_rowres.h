@@ -270,7 +270,7 @@ __device__ __forceinline__ float eval_tile(const TiledProb &tp, const float *s_r
       }
       float sm[3];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) sm[k] = m.get(k) - static_cast<float>(ps.padc[k]);
+      for (int k = 0; k < 3; ++k) sm[k] = m.get_minus(k, ps.padc[k]);
       F += finalize_kind<float>(ps.kind, sm, m.p, ps.n);
     }
     __syncthreads();
@@ -396,7 +396,7 @@ __device__ __forceinline__ float eval_tile(const TiledProb &tp, const float *s_r
           const float co = __shfl_xor(m.c[0], sh, 64);
           acc_merge(m, 0, so, co);
         }
-        float sm[3] = {m.get(0) - static_cast<float>(ps.padc[0]), 0.0f, 0.0f};
+        float sm[3] = {m.get_minus(0, ps.padc[0]), 0.0f, 0.0f};
         fr += finalize_kind<float>(ps.kind, sm, 1.0f, ps.n);
       }
       if (lane == 0) s_red[rr * kSlots] = fr;

@@ -659,7 +659,7 @@ __global__ __launch_bounds__(256) void k_tiled_finalize(TiledProb tp, const type
     }
     T sm[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) sm[k] = a.get(k) - T(sg.padc[k]);
+    for (int k = 0; k < 3; ++k) sm[k] = a.get_minus(k, sg.padc[k]);
     F += finalize_any<T>(sg.kind, sm, a.p, sg.n);
   }
   if (live) out[row] = F + T(tp.bias);
@@ -759,7 +759,7 @@ __global__ __launch_bounds__(256) void k_tiled_finalize_pairs(TiledProb tp, cons
     if (lane == 0) {
       T s[3];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) s[k] = a.get(k) - T(sg.padc[k]);
+      for (int k = 0; k < 3; ++k) s[k] = a.get_minus(k, sg.padc[k]);
       F += finalize_any<T>(sg.kind, s, a.p, sg.n);
     }
   }

@@ -5,14 +5,15 @@
 #include <hip/hip_runtime.h>
 
 #include "problem.h"
+#include "schwefel_series.h"
 
 namespace curob {
 
 // Up to three sums and one product per row.  Terms are first added plainly in groups of four
 // (one accumulator fragment); the group sums then enter a running FP32 sum that is
 // Kahan-compensated for the families whose terms have mixed signs and can cancel (Weierstrass,
-// Schwefel -- whose sum cancels against 418.98 n near the optimum --, Ackley's cosine sum,
-// Lunacek, HappyCat, HGBat; KindTraits::kahan).  Sums of non-negative terms (sphere family
+// Schwefel, Ackley's cosine sum, Lunacek, HappyCat, HGBat; KindTraits::kahan).  What padded
+// positions added is removed before the compensation is folded in (Acc::get_minus).  Sums of non-negative terms (sphere family
 // including the 1e6-weighted elliptic, Rastrigin, Rosenbrock, Griewank, step, ...) are added
 // plainly: with no cancellation the relative error of an n-term FP32 sum stays below
 // n x 2^-24 (6e-6 at n = 100, 6e-5 at n = 1000, against the 1e-4 bar), and the lanes' partial
@@ -38,7 +39,17 @@ struct Acc {
     }
   }
   __device__ __forceinline__ T get(int k) const { return s[k] - c[k]; }
+  // The sum minus a constant d (what padded positions added), taken before the compensation
+  // is folded in: when the sum and d nearly cancel, s - d_hi is exact (Sterbenz) and the
+  // compensation and the rounding remainder of d survive, instead of vanishing in the rounding
+  // of s - c to the sum's own ulp.
+  __device__ __forceinline__ T get_minus(int k, double d) const {
+    const T dh = T(d);
+    const T dl = T(d - static_cast<double>(dh));
+    return ((s[k] - dh) - c[k]) - dl;
+  }
 };
+
 
 // FP64 cos(2 pi t) for t in [-1/2, 1/2], branch free: cos(2 pi t) = -cos(2 pi (1/2 - |t|))
 // folds t onto [0, 1/4], where x = 2 pi t <= pi/2 and the Taylor series of cos in x^2 up to the
@@ -109,10 +120,14 @@ __device__ __forceinline__ T t_abs(T v) {
   if constexpr (sizeof(T) == 4) return __builtin_fabsf(v); else return __builtin_fabs(v);
 }
 
-// Modified Schwefel g1 of Eq. (basic_schwefel), branch free, on w = z + 420.9687... (the
-// tables fold the constant into c').  With a = |w|: for a <= 500 the value is w sin(sqrt a);
-// beyond, both outer branches fold a back to u = 500 - mod(a, 500) and subtract
-// (a - 500)^2 / (10000 n): g1 = sign(w) u sin(sqrt u) - penalty.
+// One Schwefel term 418.9829 - g1(w) of Eq. (basic_schwefel), branch free, on w = z +
+// 420.9687... (the tables fold the constant into c').  With a = |w|: for a <= 500 g1 is
+// w sin(sqrt a); beyond, both outer branches fold a back to u = 500 - mod(a, 500) and subtract
+// (a - 500)^2 / (10000 n): g1 = sign(w) u sin(sqrt u) - penalty.  Summing 418.9829 - g1 per
+// term (the function is the sum of these) keeps the terms small near the optimum, where
+// 418.9829 n and the sum of g1 would cancel to the ulp of 418.9829 n.  In FP32 the constant is
+// fl32(418.9829), the finalisation adds n (418.9829 - fl32(418.9829)), and within |z| < 6 of the
+// optimum (z = w - 420.9687...) the term comes from the fitted series of schwefel_series.h.
 template <typename T>
 __device__ __forceinline__ T schwefel_g1(T w, T inv10000n) {
   const T a = t_abs(w);
@@ -127,7 +142,21 @@ __device__ __forceinline__ T schwefel_g1(T w, T inv10000n) {
     // the hardware sine's domain, so no range reduction is needed.  The hardware square root
     // (1 ulp) moves the phase by at most 23 x 2^-23 rad, the order of the revolution rounding.
     const float sn = __builtin_amdgcn_sinf(__builtin_amdgcn_sqrtf(u) * 0.15915494309189535f);
-    return __builtin_copysignf(u, w) * sn - d * d * inv10000n;
+    // C - g1 with the product rounded once
+    const float direct = __builtin_fmaf(-__builtin_copysignf(u, w), sn, static_cast<float>(kSchwefelC)) + d * d * inv10000n;
+    // near the optimum of g1 (|z| < rho, z = w - w*: exact up to the rounding of w, whose effect
+    // on the term is second order there) the fitted series T0 + z^2 Q(z / rho): every term of a
+    // row at the optimum shares one argument, so the direct form's roundings of sqrt, phase and
+    // sine (~4e-5 per term) would add up over the row
+    constexpr float kW = static_cast<float>(kind_zshift(K_SCHWEFEL));
+    constexpr float kWErr = static_cast<float>(static_cast<double>(kW) - kind_zshift(K_SCHWEFEL));
+    const float z = (w - kW) + kWErr;
+    const float t = z * kSchwefelInvRho;
+    float q = kSchwefelQ[5];
+#pragma unroll
+    for (int j = 4; j >= 0; --j) q = __builtin_fmaf(q, t, kSchwefelQ[j]);
+    const float series = __builtin_fmaf(z * z, q, kSchwefelT0);
+    return __builtin_fabsf(z) < kSchwefelRho ? series : direct;
   } else {
     T m = a - T(500) * t_floor(a * T(0.002));  // mod(a, 500); the floor may be off by one
     m = m < T(0) ? m + T(500) : m;
@@ -136,7 +165,7 @@ __device__ __forceinline__ T schwefel_g1(T w, T inv10000n) {
     const T d = a - T(500);
     const T pen = far ? d * d * inv10000n : T(0);
     const T g = u * sin_rad(t_sqrt(u));
-    return (w < T(0) ? -g : g) - pen;
+    return T(kSchwefelC) - (w < T(0) ? -g : g) + pen;
   }
 }
 
@@ -214,7 +243,7 @@ __device__ __forceinline__ void phi(T (&v)[3], T &p, T z, T zn, T coef, T prm) {
     const T e = z - T(1);
     v[0] += T(100) * d * d + e * e;
   } else if constexpr (KIND == K_SCHWEFEL) {
-    v[0] += schwefel_g1(z, prm);  // z carries the 420.9687... offset
+    v[0] += schwefel_g1(z, prm);  // z carries the 420.9687... offset: w
   } else if constexpr (KIND == K_KATSUURA) {
     T t = T(0), pj = T(1);
 #pragma unroll 4
@@ -233,14 +262,16 @@ __device__ __forceinline__ void phi(T (&v)[3], T &p, T z, T zn, T coef, T prm) {
     v[0] += z * z;
     v[1] += cos_2pi(z);
   } else if constexpr (KIND == K_HAPPYCAT) {
-    // z^2 - 1 per term: near the optimum z ~ -1 and sum z^2 - n would cancel to ulps of n
-    v[0] += __builtin_fma(z, z, T(-1));
+    // on w = z + 1: z^2 - 1 = w (w - 2) and z = w - 1.  Near the optimum w -> 0 and these
+    // terms keep their relative precision, where sum z^2 - n cancels to ulps of n
+    v[0] += z * (z - T(2));
     v[1] += z;
   } else if constexpr (KIND == K_HGBAT) {
-    // (sum z^2)^2 - (sum z)^2 = sum(z^2 + z) * sum(z^2 - z), each term rounded once: near the
-    // optimum (z ~ -1) the two squares are ~n^2 and cancel, while the factors stay accurate
-    v[0] += __builtin_fma(z, z, z);
-    v[1] += __builtin_fma(z, z, -z);
+    // on w = z + 1: (sum z^2)^2 - (sum z)^2 = sum(z^2 + z) sum(z^2 - z) with z^2 + z = w (w - 1)
+    // and z^2 - z = (w - 1)(w - 2).  Near the optimum the first factor is small and stays
+    // accurate (the two squares, each ~n^2, would cancel)
+    v[0] += z * (z - T(1));
+    v[1] += (z - T(1)) * (z - T(2));
   } else if constexpr (KIND == K_F6) {
     const T r2 = z * z + zn * zn;
     const T sn = sin_rad(t_sqrt(r2));
@@ -270,7 +301,8 @@ __device__ __forceinline__ T finalize(const T (&s)[3], T p, int n) {
     const T t = s[0] / (nn - T(1));
     return t * t;
   } else if constexpr (KIND == K_SCHWEFEL) {
-    return T(418.9829) * nn - s[0];
+    // s[0] = sum (C - g1) with C = 418.9829 rounded to T
+    return s[0] + nn * T(kSchwefelC - static_cast<double>(T(kSchwefelC)));
   } else if constexpr (KIND == K_KATSUURA) {
     const T c = T(10) / (nn * nn);
     return c * p - c;
@@ -280,8 +312,9 @@ __device__ __forceinline__ T finalize(const T (&s)[3], T p, int n) {
   } else if constexpr (KIND == K_ACKLEY) {
     return T(-20) * t_exp(T(-0.2) * t_sqrt(s[0] / nn)) - t_exp(s[1] / nn) + T(20) + T(2.71828182845904523536);
   } else if constexpr (KIND == K_HAPPYCAT) {
-    // s[0] = sum(z^2 - 1), s[1] = sum z
-    return t_pow(t_abs(s[0]), T(0.25)) + (T(0.5) * (s[0] + nn) + s[1]) / nn + T(0.5);
+    // s[0] = sum(z^2 - 1) = sum z^2 - n, s[1] = sum w = sum z + n:
+    // (0.5 sum z^2 + sum z) / n + 0.5 = (0.5 s[0] + s[1]) / n
+    return t_pow(t_abs(s[0]), T(0.25)) + (T(0.5) * s[0] + s[1]) / nn;
   } else if constexpr (KIND == K_HGBAT) {
     // s[0] = sum(z^2 + z), s[1] = sum(z^2 - z): sum z^2 = (s0 + s1)/2, sum z = (s0 - s1)/2
     return t_sqrt(t_abs(s[0] * s[1])) + (T(0.75) * s[0] - T(0.25) * s[1]) / nn + T(0.5);

@@ -91,6 +91,7 @@ bool needs_six_products(int base, int n) {
   switch (base) {
     case 3: case 7: case 8: case 12: case 13: case 16: case 17: return true;
     case 2: return n < 50;
+    case 4: return n < 10;  // bent cigar: with few variables one or two 1e6-weighted z carry f
     case 14: return n < 10;
     default: return false;
   }

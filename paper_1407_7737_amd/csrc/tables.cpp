@@ -188,8 +188,8 @@ bool build_host_tables(const Problem &p, int path, HostTables &ht, std::string &
   ht.goff.assign(pad16(KT * KW * 2) / 2, static_cast<uint16_t>(D * esz));
   for (int pp = 0; pp < D; ++pp) ht.goff[pp] = static_cast<uint16_t>(order[pp] * esz);
   // per packed position: c' = c - s (Q o_lo)_p, coefficient, formula successor.  Padding gets
-  // z = 0 (Weierstrass: -1/2) and neutral coefficients.  Schwefel's g1 takes z + 420.9687..., folded into c' (its
-  // padding then gives w = 0, where g1 vanishes).
+  // z = 0 (Weierstrass: -1/2) and neutral coefficients.  The family's constant shift of z
+  // (Schwefel's 420.9687..., HappyCat's and HGBat's 1) is folded into c'; their padding gives w = 0.
   ht.cz.assign(pad16(Mp * esz), 0);
   ht.coef.assign(pad16(Mp * esz), 0);
   ht.succ.assign(pad16(Mp * 2) / 2, static_cast<int16_t>(-1));
@@ -209,7 +209,7 @@ bool build_host_tables(const Problem &p, int path, HostTables &ht, std::string &
     } else {
       corr = s * olo[i];
     }
-    store(ht.cz, pp, c - corr + (kind == K_SCHWEFEL ? 420.9687462275036 : 0.0));
+    store(ht.cz, pp, c - corr + kind_zshift(kind));
     double cf = formula_coef(base, i, D);
     if (kind == K_GRIEWANK) cf /= 2.0 * M_PI;  // the cosine takes revolutions
     store(ht.coef, pp, cf);
@@ -284,12 +284,13 @@ bool build_host_tables(const Problem &p, int path, HostTables &ht, std::string &
   pb.bias = p.fopt;
   pb.kparam = 10.0 / std::pow(static_cast<double>(D), 1.2);
   pb.scale = s;
-  // what the padded positions (z = 0, or w = 0 for Schwefel) add to each sum
+  // what the padded positions (z = 0, or w = 0 for the shifted families) add to each sum
   const double npad = static_cast<double>(Mp - D);
   pb.padc[0] = pb.padc[1] = pb.padc[2] = 0.0;
   if (kind == K_WEIERSTRASS) pb.padc[0] = npad * (2.0 - 9.5367431640625e-07);   // sum_k a^k cos(0)
   if (kind == K_ACKLEY) pb.padc[1] = npad;                                          // cos(0) = 1
-  if (kind == K_HAPPYCAT) pb.padc[0] = -npad;                                       // 0^2 - 1
+  if (kind == K_HGBAT) pb.padc[1] = 2.0 * npad;                                     // (0 - 1)(0 - 2)
+  if (kind == K_SCHWEFEL) pb.padc[0] = npad * (f64 ? kSchwefelC : static_cast<double>(static_cast<float>(kSchwefelC)));
   if (kind == K_LUNACEK) {
     pb.padc[0] = 6.25 * npad;  // (0 - 2.5)^2
     pb.padc[1] = 6.25 * npad;  // (0 + 2.5)^2

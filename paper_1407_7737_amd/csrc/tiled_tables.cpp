@@ -116,8 +116,9 @@ hipError_t build_tiled(const Problem &p, int path, TiledDev &td, std::string &er
         const double qv = B.Q ? (*B.Q)[static_cast<size_t>(a) * B.n + c] : (a == c ? 1.0 : 0.0);
         corr += qv * olo[orig[B.off + c]];
       }
-      // Schwefel's g1 takes z + 420.9687..., folded into c' (padding gives w = 0, g1 = 0)
-      store(cz, pp, sg.c - B.s * corr + (kind == K_SCHWEFEL ? 420.9687462275036 : 0.0));
+      // the family's constant shift of z (Schwefel, HappyCat, HGBat) is folded into c'
+      // (padding gives w = 0)
+      store(cz, pp, sg.c - B.s * corr + kind_zshift(kind));
       const int n_f = hybrid ? sg.n : D;
       double cf = formula_coef(sg.base, idx_in_seg[pp], n_f);
       if (kind == K_GRIEWANK) cf /= 2.0 * M_PI;  // the cosine takes revolutions
@@ -238,7 +239,8 @@ hipError_t build_tiled(const Problem &p, int path, TiledDev &td, std::string &er
     ts.padc[0] = ts.padc[1] = ts.padc[2] = 0.0;
     if (ts.kind == K_WEIERSTRASS) ts.padc[0] = npad * (2.0 - 9.5367431640625e-07);
     if (ts.kind == K_ACKLEY) ts.padc[1] = npad;
-    if (ts.kind == K_HAPPYCAT) ts.padc[0] = -npad;
+    if (ts.kind == K_HGBAT) ts.padc[1] = 2.0 * npad;
+    if (ts.kind == K_SCHWEFEL) ts.padc[0] = npad * (f64 ? kSchwefelC : static_cast<double>(static_cast<float>(kSchwefelC)));
     if (ts.kind == K_LUNACEK) {
       ts.padc[0] = 6.25 * npad;
       ts.padc[1] = 6.25 * npad;

@@ -25,7 +25,7 @@ SIX_PRODUCTS = {3, 7, 8, 12, 13, 16, 17}
 
 
 def six(fid, dim):
-    return fid in SIX_PRODUCTS or (fid == 14 and dim < 10) or (fid == 2 and dim < 50)
+    return fid in SIX_PRODUCTS or (fid in (4, 14) and dim < 10) or (fid == 2 and dim < 50)
 
 
 def say(*a):
