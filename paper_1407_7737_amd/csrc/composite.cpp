@@ -17,7 +17,7 @@ hipError_t launch_tiled_f32(int, const TiledProb &, const void *, void *, int, i
 hipError_t launch_tiled_f64(int, const TiledProb &, const void *, void *, int, int, void *, void *, void *, hipStream_t);
 hipError_t launch_rowres_split(int, const TiledProb &, const void *, void *, int, int, hipStream_t);
 hipError_t launch_rowres_split6(int, const TiledProb &, const void *, void *, int, int, hipStream_t);
-hipError_t launch_rowres_comp(const void *desc, int nc, int Dpmax, int S, int CB, const float *x, int n, int D,
+hipError_t launch_rowres_comp(const void *desc, int nc, int Dpmax, int S, const float *x, int n, int D,
                               const double *o64, const double *sig, const double *lam, const double *cb, double fopt,
                               float *out, int num_cu, hipStream_t st);
 hipError_t launch_blend(bool f64, const void *x, int n, int D, int nc, const double *o, const double *sigma,
@@ -36,9 +36,10 @@ hipError_t launch_tiled(int path, int kind_hint, const TiledProb &tp, const void
 }
 
 bool rowres_fits(const TiledProb &tp, int path) {
-  if (!is_split(path) || tp.rowwise || tp.goff == nullptr || tp.D * 4 >= 65536) return false;
-  const int CB = tp.any_pairwise ? 1 : 2;
-  return rowres::carve(tp.Dp, tp.S, CB, CB == 1).total <= kMaxLdsBytes;
+  if (!is_split(path) || tp.rowwise || tp.goff == nullptr || tp.D > rowres::kMaxD) return false;
+  // a block with pair terms writes its z over the rows: it must finish in one pass
+  if (tp.pair_mtiles_max > rowres::kPassMTiles) return false;
+  return rowres::carve(tp.Dp, tp.S, split_terms(path)).total <= kMaxLdsBytes;
 }
 
 hipError_t launch_rowres(int path, int kind_hint, const TiledProb &tp, const void *x, void *out, int n, int num_cu,
@@ -161,14 +162,21 @@ hipError_t build_composite(const Problem &p, CompositeDev &cd, std::string &err)
   if ((e = up(p.lambda, &cd.lam)) != hipSuccess) return e;
   if ((e = up(p.cbias, &cd.cb)) != hipSuccess) return e;
   // the fused composition kernel: every component above the resident range, rotated ones on the
-  // row-resident kernel, unrotated ones without pair terms
-  bool fused = p.dim * 4 < 65536;
-  int dpmax = 0, cbn = 2;
+  // row-resident kernel, unrotated ones without pair terms, at most one component with pair
+  // terms (its z overwrites the staged rows, so it runs last), and the rotation tiles of all
+  // components together small enough to stay in a die's L2 (4 MiB) next to the streaming rows.
+  // Every row tile of the fused kernel walks all components, so larger tile sets would go back
+  // to the MALL on every tile; separate launches then keep one component's tiles in L2 at a time
+  // and re-read X instead (D = 1000, eight components: 0.56 ms separate, 0.82 ms fused).
+  constexpr int kFusedTileKiB = 2048;
+  bool fused = p.dim <= rowres::kMaxD;
+  int dpmax = 0, npairs = 0, tile_kib = 0;
   for (const auto &cc : cd.comps) {
     if (cc.resident) {
       fused = false;
       break;
     }
+    npairs += cc.tiled[PATH_SPLIT].tp.any_pairwise ? 1 : 0;
     for (int path : {PATH_SPLIT, PATH_SPLIT6}) {
       const TiledProb &tp = cc.tiled[path].tp;
       if (tp.rowwise) {
@@ -176,20 +184,27 @@ hipError_t build_composite(const Problem &p, CompositeDev &cd, std::string &err)
       } else {
         if (!rowres_fits(tp, path)) fused = false;
         dpmax = std::max(dpmax, tp.Dp);
-        if (tp.any_pairwise) cbn = 1;
+        if (path == (cc.six ? PATH_SPLIT6 : PATH_SPLIT)) tile_kib += tp.qfrag_kib;
       }
     }
   }
-  if (fused && rowres::comp_carve(dpmax, lds_stride(p.dim, 0), cbn).total <= kMaxLdsBytes) {
+  if (npairs > 1 || tile_kib > kFusedTileKiB) fused = false;
+  if (fused && rowres::comp_carve(dpmax, lds_stride(p.dim, 0)).total <= kMaxLdsBytes) {
+    // evaluation order: components without pair terms first
+    std::vector<int> order;
+    for (int pass = 0; pass < 2; ++pass)
+      for (int i = 0; i < nc; ++i)
+        if ((cd.comps[i].tiled[PATH_SPLIT].tp.any_pairwise != 0) == (pass == 1)) order.push_back(i);
     for (int mode = 0; mode < 3; ++mode) {
       std::vector<rowres::CompDesc> desc(cd.comps.size());
-      for (size_t i = 0; i < cd.comps.size(); ++i) {
-        const auto &cc = cd.comps[i];
+      for (size_t k = 0; k < order.size(); ++k) {
+        const auto &cc = cd.comps[order[k]];
         const bool six = mode == 0 ? cc.six : mode == 2;
         const TiledProb &tp = cc.tiled[six ? PATH_SPLIT6 : PATH_SPLIT].tp;
-        desc[i].tp = tp;
-        desc[i].six = six ? 1 : 0;
-        desc[i].unrotated = tp.rowwise;
+        desc[k].tp = tp;
+        desc[k].six = six ? 1 : 0;
+        desc[k].unrotated = tp.rowwise;
+        desc[k].index = order[k];
       }
       void *d = nullptr;
       if ((e = hipMalloc(&d, desc.size() * sizeof(rowres::CompDesc))) != hipSuccess) return e;
@@ -201,7 +216,6 @@ hipError_t build_composite(const Problem &p, CompositeDev &cd, std::string &err)
     cd.rr_ok = true;
     cd.rr_dpmax = dpmax;
     cd.rr_S = lds_stride(p.dim, 0);
-    cd.rr_cb = cbn;
   }
   cd.ready = true;
   return hipSuccess;
@@ -263,7 +277,7 @@ hipError_t launch_composite(int path, bool split_auto, const CompositeDev &cd, c
   // compositions with every component on the row-resident kernel: one fused launch
   if (cd.is_composition && cd.rr_ok && is_split(path)) {
     const int mode = split_auto ? 0 : (path == PATH_SPLIT6 ? 2 : 1);
-    return launch_rowres_comp(cd.rr_desc[mode], static_cast<int>(cd.comps.size()), cd.rr_dpmax, cd.rr_S, cd.rr_cb,
+    return launch_rowres_comp(cd.rr_desc[mode], static_cast<int>(cd.comps.size()), cd.rr_dpmax, cd.rr_S,
                               static_cast<const float *>(x), n, cd.dim, cd.o64, cd.sig, cd.lam, cd.cb, cd.fopt,
                               static_cast<float *>(out), num_cu, st);
   }

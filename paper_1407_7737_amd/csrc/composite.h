@@ -36,7 +36,7 @@ struct CompositeDev {
   // descriptors per split mode (0: three or six products per component, 1: three, 2: six)
   bool rr_ok = false;
   const void *rr_desc[3] = {nullptr, nullptr, nullptr};
-  int rr_dpmax = 0, rr_S = 0, rr_cb = 2;
+  int rr_dpmax = 0, rr_S = 0;
   void release();
 };
 

@@ -1,19 +1,24 @@
 // eval_rowres.h -- fused evaluation for dimensions above the resident kernel's range on the
-// split paths (basic functions and hybrids, Sec. 5), with the population rows resident in LDS.
+// split paths (basic functions and hybrids, Sec. 5; the components of a composition, Sec. 6),
+// with the population rows resident in LDS.
 //
-// A workgroup of eight waves holds 16 * CB population rows in LDS (x as read, one row at a time
-// with buffer loads that write LDS) and computes every output of the packed block-diagonal
-// rotation for them:
-//   - for each rotation block, each wave takes m-tiles (16 outputs) of the block, up to three at
-//     a time, and walks the block's k steps: the B operand (y = x - o_hi of 8 packed positions
-//     per lane, cut into bf16 terms) is gathered from the LDS rows once per step and feeds all
-//     of the wave's m-tiles; the rotation tiles (A operand) stream from L2, two steps ahead;
+// A workgroup of eight waves holds 32 population rows in LDS (x as read) and computes every
+// output of the packed block-diagonal rotation for them:
+//   - for each rotation block, each wave takes up to three m-tiles (16 outputs) of the block and
+//     all waves walk the block's k steps together.  The B operand of a k step (y = x - o_hi at
+//     32 packed positions for the 32 rows, cut into bf16 terms) is produced once per workgroup,
+//     one pair of positions of one row per thread, into a two-slot LDS ring in MFMA operand
+//     order, one barrier per step; every wave then reads it with one 16-byte LDS read per
+//     (column block, term).  The rotation tiles (A operand) stream from L2, two steps ahead;
 //   - z = acc + c' then the formula's per-element terms go into the wave's compensated row
-//     sums (formulas with pair terms instead write z to an LDS copy in packed order);
+//     sums.  Formulas with pair terms instead write z back into the LDS rows, at the slot of
+//     the position's own variable (the block's variables are read by no later step), and the
+//     pair terms are summed from there once every block is done;
 //   - row sums of all waves meet in LDS, in wave order, and wave 0 finalises each formula
-//     segment of its rows; pair terms are summed from the LDS copy of z at the end.
-// X is read from HBM once, nothing goes through scratch memory, and the result row is written
-// directly.  Persistent grid: each workgroup walks row tiles with a stride of the grid.
+//     segment of its rows.
+// The rows reach LDS through buffer loads that write LDS directly.  X is read from HBM once,
+// nothing goes through scratch memory, and the result row is written directly.  Persistent
+// grid: each workgroup walks row tiles with a stride of the grid.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -37,22 +42,32 @@ typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
 constexpr int kWaves = 8;
 constexpr int kThreads = 64 * kWaves;
-constexpr int kMW = 3;      // m-tiles of one block per wave pass (one B gather feeds them all)
+constexpr int kMW = 3;      // m-tiles of one block per wave pass (one B chunk feeds them all)
 constexpr int kSlots = 8;   // per (wave, row) partial: s0 c0 s1 c1 s2 c2 product pad
+constexpr int kCB = 2;      // 16-row column blocks per tile
+constexpr int kRows = 16 * kCB;
+// m-tiles one pass covers; a block with pair terms must fit one pass (its z overwrites rows
+// that a second pass would read again)
+constexpr int kPassMTiles = kWaves * kMW;
 
-// LDS carve: packed-position tables, the rows, the z copy (pairwise), the per-wave partials.
+// Bytes of one ring slot: kCB column blocks x NT terms x 64 lanes x 16 bytes.
+__host__ __device__ constexpr int ring_slot_bytes(int NT) { return kCB * NT * 64 * 16; }
+
+// Rows this wide fit the LDS carve next to the tables, the ring and the partials.
+constexpr int kMaxD = 1088;
+
+// LDS carve: packed-position tables, the rows, the B ring, the per-wave partials.
 struct Carve {
-  int goff, ohp, rows, zc, red, total;
+  int goff, ohp, rows, ring, red, total;
 };
-__host__ __device__ inline Carve carve(int Dp, int S, int CB, bool pairs) {
+__host__ __device__ inline Carve carve(int Dp, int S, int NT) {
   Carve c;
-  const int R = 16 * CB;
   c.goff = 0;
   c.ohp = round16(Dp * 2);
   c.rows = c.ohp + round16(Dp * 4);
-  c.zc = c.rows + round16(R * S * 4);
-  c.red = c.zc + (pairs ? round16(R * Dp * 4) : 0);
-  c.total = c.red + kWaves * R * kSlots * 4;
+  c.ring = c.rows + round16(kRows * S * 4);
+  c.red = c.ring + 2 * ring_slot_bytes(NT);
+  c.total = c.red + kWaves * kRows * kSlots * 4;
   return c;
 }
 
@@ -77,31 +92,6 @@ __device__ __forceinline__ float seg_param(const TiledSeg &sg) {
   return 0.0f;
 }
 
-// Cuts 8 gathered y into the split path's bf16 terms (y - hi and the next residual are exact).
-template <int NT>
-__device__ __forceinline__ void cut8(const float (&y)[8], bf16x8 (&t)[NT]) {
-#pragma unroll
-  for (int e = 0; e < 8; e += 2) {
-    const f32x2 v = {y[e], y[e + 1]};
-    const bf16x2 h = __builtin_convertvector(v, bf16x2);
-    const f32x2 r1 = v - __builtin_convertvector(h, f32x2);
-    t[0][e] = h[0];
-    t[0][e + 1] = h[1];
-    if constexpr (NT == 3) {
-      const bf16x2 m = __builtin_convertvector(r1, bf16x2);
-      const bf16x2 l = __builtin_convertvector(r1 - __builtin_convertvector(m, f32x2), bf16x2);
-      t[1][e] = m[0];
-      t[1][e + 1] = m[1];
-      t[2][e] = l[0];
-      t[2][e + 1] = l[1];
-    } else {
-      const bf16x2 l = __builtin_convertvector(r1, bf16x2);
-      t[1][e] = l[0];
-      t[1][e + 1] = l[1];
-    }
-  }
-}
-
 // The split products of one (m-tile, column block) for one k step: A terms a[], B terms b[].
 template <int NT>
 __device__ __forceinline__ f32x4 products(const bf16x8 (&a)[NT], const bf16x8 (&b)[NT], f32x4 acc) {
@@ -119,6 +109,38 @@ __device__ __forceinline__ f32x4 products(const bf16x8 (&a)[NT], const bf16x8 (&
     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[0], acc, 0, 0, 0);
   }
   return acc;
+}
+
+// Product st of products<NT> alone (st fixed at compile time after unrolling).
+template <int NT>
+__device__ __forceinline__ f32x4 product_stage(int st, const bf16x8 (&a)[NT], const bf16x8 (&b)[NT], f32x4 acc) {
+  if constexpr (NT == 3) {
+    constexpr int ia[6] = {2, 1, 0, 1, 0, 0}, ib[6] = {0, 1, 2, 0, 1, 0};
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ia[st]], b[ib[st]], acc, 0, 0, 0);
+  } else {
+    constexpr int ia[3] = {1, 0, 0}, ib[3] = {0, 1, 0};
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ia[st]], b[ib[st]], acc, 0, 0, 0);
+  }
+}
+
+// Cuts the pair y of one thread's share of a B step into NT bf16 terms (y - hi and the next
+// residual are exact in FP32) and writes them at dst, the pair's place in a ring slot: term u of
+// lane slot l of column block cb sits at byte ((cb NT + u) 64 + l) 16 of the slot, the 16-byte
+// B fragment of that MFMA lane (the 32 positions x 32 rows of a step: 512 threads, one pair each).
+template <int NT>
+__device__ __forceinline__ void cut_pair(unsigned char *dst, f32x2 y) {
+  const bf16x2 h = __builtin_convertvector(y, bf16x2);
+  const f32x2 r1 = y - __builtin_convertvector(h, f32x2);
+  *reinterpret_cast<uint32_t *>(dst) = __builtin_bit_cast(uint32_t, h);
+  if constexpr (NT == 3) {
+    const bf16x2 m = __builtin_convertvector(r1, bf16x2);
+    const bf16x2 lo = __builtin_convertvector(r1 - __builtin_convertvector(m, f32x2), bf16x2);
+    *reinterpret_cast<uint32_t *>(dst + 64 * 16) = __builtin_bit_cast(uint32_t, m);
+    *reinterpret_cast<uint32_t *>(dst + 2 * 64 * 16) = __builtin_bit_cast(uint32_t, lo);
+  } else {
+    const bf16x2 lo = __builtin_convertvector(r1, bf16x2);
+    *reinterpret_cast<uint32_t *>(dst + 64 * 16) = __builtin_bit_cast(uint32_t, lo);
+  }
 }
 
 // Formula terms of one accumulator fragment (4 packed positions from pos) into the lane's
@@ -170,19 +192,19 @@ __device__ __forceinline__ void flush(Acc<float> &a, float *slot, int q) {
   a.init();
 }
 
-// Pair terms of one pairwise segment for one row, from the packed z copy zr; lanes over the
-// segment's positions.
+// Pair terms of one pairwise segment for one row, from z written back over the row's x (the
+// slot of each position's variable); lanes over the segment's positions.
 template <int K>
-__device__ __forceinline__ void pair_row(const TiledProb &tp, const TiledSeg &sg, const float *zr, float prm, int lane,
-                                         Acc<float> &a) {
+__device__ __forceinline__ void pair_row(const TiledProb &tp, const TiledSeg &sg, const unsigned char *zr,
+                                         const uint16_t *s_goff, float prm, int lane, Acc<float> &a) {
   const float *coefp = static_cast<const float *>(tp.coef);
   for (int p0 = sg.p0; p0 < sg.p1; p0 += 64) {
     const int pp = p0 + lane;
     const int pc = pp < sg.p1 ? pp : sg.p1 - 1;
     const int sp = tp.succ[pc];
     const int gi = tp.gidx[pc];
-    const float z = zr[pc];
-    const float zn = zr[sp >= 0 ? sp : pc];
+    const float z = *reinterpret_cast<const float *>(zr + s_goff[pc]);
+    const float zn = *reinterpret_cast<const float *>(zr + s_goff[sp >= 0 ? sp : pc]);
     const float cf = coefp[pc];
     if (pp < sg.p1 && gi >= 0 && sp >= 0) {
       float v[3] = {0.0f, 0.0f, 0.0f};
@@ -192,13 +214,13 @@ __device__ __forceinline__ void pair_row(const TiledProb &tp, const TiledSeg &sg
   }
 }
 
-__device__ __forceinline__ void pair_row_any(const TiledProb &tp, const TiledSeg &sg, const float *zr, float prm,
-                                             int lane, Acc<float> &a) {
+__device__ __forceinline__ void pair_row_any(const TiledProb &tp, const TiledSeg &sg, const unsigned char *zr,
+                                             const uint16_t *s_goff, float prm, int lane, Acc<float> &a) {
   switch (sg.kind) {
-    case K_F7: pair_row<K_F7>(tp, sg, zr, prm, lane, a); break;
-    case K_GRIEROSEN: pair_row<K_GRIEROSEN>(tp, sg, zr, prm, lane, a); break;
-    case K_ROSENBROCK: pair_row<K_ROSENBROCK>(tp, sg, zr, prm, lane, a); break;
-    case K_F6: pair_row<K_F6>(tp, sg, zr, prm, lane, a); break;
+    case K_F7: pair_row<K_F7>(tp, sg, zr, s_goff, prm, lane, a); break;
+    case K_GRIEROSEN: pair_row<K_GRIEROSEN>(tp, sg, zr, s_goff, prm, lane, a); break;
+    case K_ROSENBROCK: pair_row<K_ROSENBROCK>(tp, sg, zr, s_goff, prm, lane, a); break;
+    case K_F6: pair_row<K_F6>(tp, sg, zr, s_goff, prm, lane, a); break;
     default: break;
   }
 }
@@ -215,55 +237,79 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t rows_rsrc(const float *x, int 
 // loads that write LDS: 16 bytes per lane when wide (D a multiple of 4, rows 16-byte aligned in
 // memory), 4 otherwise.  Lanes past the row's end are masked off, so nothing past column D - 1
 // is written.
+// The loads are non-temporal (cache policy nt): the population streams through once and should
+// not evict the rotation tiles, which every tile re-reads from L2.
+constexpr int kCachePolicyNT = 2;
 __device__ __forceinline__ void load_row(__amdgpu_buffer_rsrc_t rs, int D, float *dst, int soff, bool wide, int lane) {
   typedef __attribute__((address_space(3))) void *lds_ptr;
   if (wide) {
     for (int k0 = 0; k0 < D; k0 += 256)
       if (4 * lane < D - k0)
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_ptr)(dst + k0), 16, (k0 + 4 * lane) * 4, soff, 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_ptr)(dst + k0), 16, (k0 + 4 * lane) * 4, soff, 0,
+                                                 kCachePolicyNT);
   } else {
     for (int k0 = 0; k0 < D; k0 += 64)
       if (lane < D - k0)
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_ptr)(dst + k0), 4, (k0 + lane) * 4, soff, 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_ptr)(dst + k0), 4, (k0 + lane) * 4, soff, 0, kCachePolicyNT);
   }
 }
 
 constexpr int kWaitVmem = 0x3F70;  // s_waitcnt vmcnt(0), other counters free (gfx9 encoding)
 
+// Stages rows [row0, row0 + 32) of x (past n: zeros) at stride S, then barrier.  The zero slot
+// (column D) of every row is rewritten too: padded positions gather it.
+__device__ __forceinline__ void stage_rows(const float *x, int row0, int n, int D, int S, float *s_rows, bool wide,
+                                           int lane, int wave) {
+  const __amdgpu_buffer_rsrc_t rs = rows_rsrc(x, row0, n, D);
+  for (int rr = wave; rr < kRows; rr += kWaves) load_row(rs, D, s_rows + rr * S, rr * 4 * D, wide, lane);
+  if (threadIdx.x < kRows) s_rows[threadIdx.x * S + D] = 0.0f;
+  __builtin_amdgcn_s_waitcnt(kWaitVmem);
+  __syncthreads();
+}
+
 // One problem (basic function or hybrid) on the rows staged in LDS: every rotation block, the
-// formula terms and row sums, the pair terms.  Returns, in wave 0 lanes < 16 CB, the sum of the
+// formula terms and row sums, the pair terms.  Returns, in wave 0 lanes < 32, the sum of the
 // row's finalised segments (f without f_opt); other lanes return 0.  The problem's gather tables
-// must be in s_goff / s_ohp.  Every barrier is reached by all waves.
+// must be in s_goff / s_ohp.  Formulas with pair terms overwrite the x of their own variables
+// with z.  Every barrier is reached by all threads.
 // KIND >= 0: one formula family (basic functions); KIND < 0: family per segment at run time
 // (hybrids, composition components).  NT: bf16 terms per operand (2: three products, 3: six).
-// CB: 16-row column blocks (2; 1 when pair terms need the z copy s_z).
-template <int NT, int KIND, int CB>
-__device__ __forceinline__ float eval_tile(const TiledProb &tp, const float *s_rows, int S, const uint16_t *s_goff,
-                                           const float *s_ohp, float *s_z, float *s_red, int lane, int wave) {
-  constexpr int R = 16 * CB;
-  constexpr bool PAIRS = CB == 1;
+// AHEAD: steps the rotation tiles are requested ahead of their products (registers permitting).
+template <int NT, int KIND, int AHEAD>
+__device__ __forceinline__ float eval_tile(const TiledProb &tp, float *s_rows, int S, const uint16_t *s_goff,
+                                           const float *s_ohp, unsigned char *s_ring, float *s_red, int lane,
+                                           int wave) {
   const int r = lane & 15, q = lane >> 4;
-  const int Dp = tp.Dp;
-  const bf16x8 *qfrag = static_cast<const bf16x8 *>(tp.qfrag);
   const float *czp = static_cast<const float *>(tp.cz);
   const float *cfp = static_cast<const float *>(tp.coef);
+  constexpr int kSlot = ring_slot_bytes(NT);
+  const __amdgpu_buffer_rsrc_t qrs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(tp.qfrag), (short)0, 0x7ffffff0, 0x00020000);
+  // this thread's share of each B step: column block t / 256, lane slot l = (t / 4) % 64 (row
+  // l % 16, positions 8 (l / 16) ..), position pair e = 2 (t % 4), e + 1
+  const int pt = static_cast<int>(threadIdx.x);
+  const int pcb = pt >> 8, pl = (pt >> 2) & 63, pe = (pt & 3) * 2;
+  const int pair_pos = 8 * (pl >> 4) + pe;
+  const int pair_slot = ((pcb * NT) * 64 + pl) * 16 + pe * 2;
+  const unsigned char *prow = reinterpret_cast<const unsigned char *>(s_rows + (16 * pcb + (pl & 15)) * S);
 
   float F = 0.0f;
-  Acc<float> a[CB];
+  Acc<float> a[kCB];
 #pragma unroll
-  for (int cb = 0; cb < CB; ++cb) a[cb].init();
+  for (int cb = 0; cb < kCB; ++cb) a[cb].init();
   int seg_open = -1;  // segment whose sums the waves are accumulating
+  bool any_pairs = false;
 
   // merges the waves' sums of segment ps in wave order and finalises it (wave 0 keeps F)
   auto close_segment = [&](const TiledSeg &ps) {
 #pragma unroll
-    for (int cb = 0; cb < CB; ++cb) flush(a[cb], s_red + (wave * R + 16 * cb + r) * kSlots, q);
+    for (int cb = 0; cb < kCB; ++cb) flush(a[cb], s_red + (wave * kRows + 16 * cb + r) * kSlots, q);
     __syncthreads();
-    if (wave == 0 && lane < R) {
+    if (wave == 0 && lane < kRows) {
       Acc<float> m;
       m.init();
       for (int w = 0; w < kWaves; ++w) {
-        const float *src = s_red + (w * R + lane) * kSlots;
+        const float *src = s_red + (w * kRows + lane) * kSlots;
 #pragma unroll
         for (int k = 0; k < 3; ++k) acc_merge(m, k, src[2 * k], src[2 * k + 1]);
         m.p *= src[6];
@@ -290,82 +336,117 @@ __device__ __forceinline__ float eval_tile(const TiledProb &tp, const float *s_r
     seg_open = segi;
     const int kind = KIND >= 0 ? KIND : sg.kind;
     const bool pairseg = KIND >= 0 ? KindTraits<(KIND >= 0 ? KIND : 0)>::pairwise : sg.pairwise != 0;
+    any_pairs = any_pairs || pairseg;
     const float prm = seg_param(sg);
+    const int npass = (mts + kPassMTiles - 1) / kPassMTiles;
 
-    for (int mbase = wave; mbase < mts; mbase += kWaves * kMW) {
-      // this pass: m-tiles mbase + kWaves j of the block (inactive ones recompute the first and
-      // are discarded)
+    for (int pass = 0; pass < npass; ++pass) {
+      // this pass: m-tiles mbase + kWaves j of the block.  A slot past the block's m-tiles
+      // repeats the last m-tile and is discarded (no branch splits the step: waves 4 apart
+      // share a SIMD, and the fullest SIMD sets the pace anyway)
+      const int mbase = pass * kPassMTiles + wave;
       int mt[kMW];
-#pragma unroll
-      for (int j = 0; j < kMW; ++j) mt[j] = mbase + kWaves * j < mts ? mbase + kWaves * j : mbase;
-      const bf16x8 *qa[kMW];
-#pragma unroll
-      for (int j = 0; j < kMW; ++j) qa[j] = qfrag + static_cast<size_t>(blk.z + mt[j] * nst) * (NT * 64) + lane;
-      f32x4 acc[kMW][CB];
-#pragma unroll
-      for (int j = 0; j < kMW; ++j)
-#pragma unroll
-        for (int cb = 0; cb < CB; ++cb) acc[j][cb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-      // rotation tiles two steps ahead: a0 holds even steps, a1 odd ones
-      bf16x8 a0[kMW][NT], a1[kMW][NT];
-#pragma unroll
-      for (int j = 0; j < kMW; ++j)
-#pragma unroll
-        for (int u = 0; u < NT; ++u) {
-          a0[j][u] = qa[j][u * 64];
-          a1[j][u] = qa[j][((nst > 1 ? 1 : 0) * NT + u) * 64];
-        }
-      auto step = [&](int c, bf16x8 (&au)[kMW][NT]) {
-        // B: 8 packed positions per lane, gathered from the rows of each column block
-        const int p0 = blk.x + 32 * c + 8 * q;
-        const uint4 idx = *reinterpret_cast<const uint4 *>(s_goff + p0);
-        const uint32_t iw[4] = {idx.x, idx.y, idx.z, idx.w};
-        const f32x4 oa = *reinterpret_cast<const f32x4 *>(s_ohp + p0);
-        const f32x4 ob = *reinterpret_cast<const f32x4 *>(s_ohp + p0 + 4);
-        const float ov[8] = {oa[0], oa[1], oa[2], oa[3], ob[0], ob[1], ob[2], ob[3]};
-        bf16x8 bt[CB][NT];
-#pragma unroll
-        for (int cb = 0; cb < CB; ++cb) {
-          const unsigned char *row = reinterpret_cast<const unsigned char *>(s_rows + (16 * cb + r) * S);
-          float y[8];
-#pragma unroll
-          for (int e = 0; e < 8; e += 2) {
-            y[e] = *reinterpret_cast<const float *>(row + (iw[e >> 1] & 0xFFFFu)) - ov[e];
-            y[e + 1] = *reinterpret_cast<const float *>(row + (iw[e >> 1] >> 16)) - ov[e + 1];
-          }
-          cut8<NT>(y, bt[cb]);
-        }
-#pragma unroll
-        for (int j = 0; j < kMW; ++j)
-#pragma unroll
-          for (int cb = 0; cb < CB; ++cb) acc[j][cb] = products<NT>(au[j], bt[cb], acc[j][cb]);
-        // this register set now takes step c + 2 (clamped: past the end it reloads the last)
-        const int cn = c + 2 < nst ? c + 2 : nst - 1;
-#pragma unroll
-        for (int j = 0; j < kMW; ++j)
-#pragma unroll
-          for (int u = 0; u < NT; ++u) au[j][u] = qa[j][(static_cast<size_t>(cn) * NT + u) * 64];
-      };
-      for (int c = 0; c < nst; c += 2) {
-        step(c, a0);
-        if (c + 1 < nst) step(c + 1, a1);
-      }
-      // epilogue: z = acc + c' per position; terms into the wave's row sums, or z into the
-      // packed copy for pair terms
+      bool act[kMW];
 #pragma unroll
       for (int j = 0; j < kMW; ++j) {
-        if (mbase + kWaves * j >= mts) continue;
-        const int pm = blk.x + 16 * mt[j] + 4 * q;  // 4 consecutive packed positions
+        act[j] = mbase + kWaves * j < mts;
+        mt[j] = act[j] ? mbase + kWaves * j : mts - 1;
+      }
+      // rotation tiles through buffer loads: per-lane offset fixed, tile offset scalar
+      auto load_a = [&](bf16x8 (&au)[kMW][NT], int c) {
+#pragma unroll
+        for (int j = 0; j < kMW; ++j) {
+          const int toff = (blk.z + mt[j] * nst + c) * (NT * 1024);
+#pragma unroll
+          for (int u = 0; u < NT; ++u)
+            au[j][u] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(qrs, lane * 16 + u * 1024, toff, 0));
+        }
+      };
+      f32x4 acc[kMW][kCB];
+#pragma unroll
+      for (int j = 0; j < kMW; ++j)
+#pragma unroll
+        for (int cb = 0; cb < kCB; ++cb) acc[j][cb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+      // rotation tiles kAhead steps ahead: register set k holds the steps c with c % kAhead == k
+      // (the loads of a step are in flight while the kAhead - 1 steps before it compute)
+      constexpr int kAhead = AHEAD;
+      bf16x8 ar[kAhead][kMW][NT];
+#pragma unroll
+      for (int k = 0; k < kAhead; ++k) load_a(ar[k], k < nst ? k : nst - 1);
+      // B operand pipeline (one barrier per step): step c consumes ring slot c & 1, gathers the
+      // x of step c + 1 with offsets read one step earlier, reads the offsets of step c + 2, and
+      // writes step c + 1 into the other slot (read last at step c - 1, before the previous
+      // barrier).  Steps past the block repeat its last step into a slot nobody reads.
+      auto pos = [&](int c) { return blk.x + 32 * (c < nst ? c : nst - 1) + pair_pos; };
+      uint32_t go = *reinterpret_cast<const uint32_t *>(s_goff + pos(0));
+      f32x2 oo = *reinterpret_cast<const f32x2 *>(s_ohp + pos(0));
+      {
+        const f32x2 y = f32x2{*reinterpret_cast<const float *>(prow + (go & 0xFFFFu)),
+                              *reinterpret_cast<const float *>(prow + (go >> 16))} - oo;
+        cut_pair<NT>(s_ring + pair_slot, y);
+      }
+      go = *reinterpret_cast<const uint32_t *>(s_goff + pos(1));
+      oo = *reinterpret_cast<const f32x2 *>(s_ohp + pos(1));
+      __syncthreads();
+      auto step = [&](int c, bf16x8 (&au)[kMW][NT]) {
+        const unsigned char *slot = s_ring + (c & 1) * kSlot;
+        bf16x8 bt[kCB][NT];
+#pragma unroll
+        for (int cb = 0; cb < kCB; ++cb)
+#pragma unroll
+          for (int u = 0; u < NT; ++u) bt[cb][u] = *reinterpret_cast<const bf16x8 *>(slot + ((cb * NT + u) * 64 + lane) * 16);
+        const f32x2 xv = f32x2{*reinterpret_cast<const float *>(prow + (go & 0xFFFFu)),
+                               *reinterpret_cast<const float *>(prow + (go >> 16))};
+        const uint32_t go2 = *reinterpret_cast<const uint32_t *>(s_goff + pos(c + 2));
+        const f32x2 oo2 = *reinterpret_cast<const f32x2 *>(s_ohp + pos(c + 2));
+        __builtin_amdgcn_sched_barrier(0);
+        // the product stages outermost: kMW * kCB independent accumulators between two
+        // products into the same one
+#pragma unroll
+        for (int st = 0; st < (NT == 3 ? 6 : 3); ++st)
+#pragma unroll
+          for (int j = 0; j < kMW; ++j)
+#pragma unroll
+            for (int cb = 0; cb < kCB; ++cb) acc[j][cb] = product_stage<NT>(st, au[j], bt[cb], acc[j][cb]);
+        // this register set now takes step c + kAhead (clamped: past the end it reloads the last)
+        load_a(au, c + kAhead < nst ? c + kAhead : nst - 1);
+        __builtin_amdgcn_sched_barrier(0);
+        cut_pair<NT>(s_ring + ((c + 1) & 1) * kSlot + pair_slot, xv - oo);
+        go = go2;
+        oo = oo2;
+        __syncthreads();
+      };
+      // whole rounds of kAhead steps without a branch (so the wait for a step's tiles counts
+      // only the loads issued before them), then the remaining steps
+      int c = 0;
+      for (; c + kAhead <= nst; c += kAhead) {
+#pragma unroll
+        for (int k = 0; k < kAhead; ++k) step(c + k, ar[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < kAhead - 1; ++k)
+        if (c + k < nst) step(c + k, ar[k]);
+      // epilogue: z = acc + c' per position; terms into the wave's row sums, or z over the x of
+      // the position's variable for pair terms (padding: z = 0 into the zero slot, unchanged)
+#pragma unroll
+      for (int j = 0; j < kMW; ++j) {
+        if (!act[j]) continue;
+        const int pm = blk.x + 16 * (mbase + kWaves * j) + 4 * q;  // 4 consecutive packed positions
         const f32x4 cz4 = *reinterpret_cast<const f32x4 *>(czp + pm);
         if (pairseg) {
-          if constexpr (PAIRS) {
+          const uint2 g2 = *reinterpret_cast<const uint2 *>(s_goff + pm);
+          const uint32_t go[4] = {g2.x & 0xFFFFu, g2.x >> 16, g2.y & 0xFFFFu, g2.y >> 16};
 #pragma unroll
-            for (int cb = 0; cb < CB; ++cb) *reinterpret_cast<f32x4 *>(s_z + (16 * cb + r) * Dp + pm) = acc[j][cb] + cz4;
+          for (int cb = 0; cb < kCB; ++cb) {
+            unsigned char *row = reinterpret_cast<unsigned char *>(s_rows + (16 * cb + r) * S);
+            const f32x4 z = acc[j][cb] + cz4;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) *reinterpret_cast<float *>(row + go[e]) = z[e];
           }
         } else {
           const f32x4 cf4 = *reinterpret_cast<const f32x4 *>(cfp + pm);
 #pragma unroll
-          for (int cb = 0; cb < CB; ++cb) {
+          for (int cb = 0; cb < kCB; ++cb) {
             if constexpr (KIND >= 0) terms<(KIND >= 0 ? KIND : 0)>(acc[j][cb], cz4, cf4, prm, a[cb]);
             else terms_any(kind, acc[j][cb], cz4, cf4, prm, a[cb]);
           }
@@ -373,23 +454,24 @@ __device__ __forceinline__ float eval_tile(const TiledProb &tp, const float *s_r
       }
     }
   }
-  // the last open segment (every segment of a basic function)
+  // the last open segment (every segment of a basic function); the barrier also orders the z
+  // written back above before the pair terms read it
   {
     const TiledSeg &ps = tp.segs[seg_open >= 0 ? seg_open : 0];
     if (!ps.pairwise) close_segment(ps);
     else __syncthreads();
   }
-  if constexpr (PAIRS) {
-    // pair terms from the z copy: each wave takes rows, lanes the positions of each pairwise
-    // segment; the row's pair value goes to slot 0 of its partials (no other use now)
-    for (int rr = wave; rr < R; rr += kWaves) {
+  if (any_pairs) {
+    // pair terms: each wave takes rows, lanes the positions of each pairwise segment; the row's
+    // pair value goes to slot 0 of its partials (no other use now)
+    for (int rr = wave; rr < kRows; rr += kWaves) {
       float fr = 0.0f;
       for (int si = 0; si < tp.nsegs; ++si) {
         const TiledSeg &ps = tp.segs[si];
         if (!ps.pairwise) continue;
         Acc<float> m;
         m.init();
-        pair_row_any(tp, ps, s_z + rr * Dp, seg_param(ps), lane, m);
+        pair_row_any(tp, ps, reinterpret_cast<const unsigned char *>(s_rows + rr * S), s_goff, seg_param(ps), lane, m);
 #pragma unroll
         for (int sh = 1; sh < 64; sh <<= 1) {
           const float so = __shfl_xor(m.s[0], sh, 64);
@@ -402,7 +484,7 @@ __device__ __forceinline__ float eval_tile(const TiledProb &tp, const float *s_r
       if (lane == 0) s_red[rr * kSlots] = fr;
     }
     __syncthreads();
-    if (wave == 0 && lane < R) F += s_red[lane * kSlots];
+    if (wave == 0 && lane < kRows) F += s_red[lane * kSlots];
     __syncthreads();
   }
   return F;
@@ -416,42 +498,28 @@ __device__ __forceinline__ void load_tables(const TiledProb &tp, uint16_t *s_gof
   }
 }
 
-// Stages rows [row0, row0 + R) of x (R = 16 CB; past n: zeros) at stride S, then barrier.
-template <int CB>
-__device__ __forceinline__ void stage_rows(const float *x, int row0, int n, int D, int S, float *s_rows, bool wide,
-                                           int lane, int wave) {
-  constexpr int R = 16 * CB;
-  const __amdgpu_buffer_rsrc_t rs = rows_rsrc(x, row0, n, D);
-  for (int rr = wave; rr < R; rr += kWaves) load_row(rs, D, s_rows + rr * S, rr * 4 * D, wide, lane);
-  __builtin_amdgcn_s_waitcnt(kWaitVmem);
-  __syncthreads();
-}
-
-// Basic function or hybrid: persistent grid over tiles of 16 CB rows.
-template <int P, int KIND, int CB>
+// Basic function or hybrid: persistent grid over tiles of 32 rows.
+template <int NT, int KIND>
 __global__ __launch_bounds__(kThreads) void k_rowres(TiledProb tp, const float *__restrict__ x, int n,
                                                      float *__restrict__ out, int wide) {
-  constexpr int R = 16 * CB;
   extern __shared__ __align__(16) unsigned char smem[];
   const int D = tp.D, S = tp.S;
-  const Carve L = carve(tp.Dp, S, CB, CB == 1);
+  const Carve L = carve(tp.Dp, S, NT);
   uint16_t *s_goff = reinterpret_cast<uint16_t *>(smem + L.goff);
   float *s_ohp = reinterpret_cast<float *>(smem + L.ohp);
   float *s_rows = reinterpret_cast<float *>(smem + L.rows);
-  float *s_z = reinterpret_cast<float *>(smem + L.zc);
+  unsigned char *s_ring = smem + L.ring;
   float *s_red = reinterpret_cast<float *>(smem + L.red);
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int ntiles = (n + kRows - 1) / kRows;
   load_tables(tp, s_goff, s_ohp);
-  // the zero slot (column D) of every row: padded positions gather it; loads never write it
-  if (threadIdx.x < R) s_rows[threadIdx.x * S + D] = 0.0f;
-  const int ntiles = (n + R - 1) / R;
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int row0 = tile * R;
+    const int row0 = tile * kRows;
     __syncthreads();  // the previous tile's readers of the rows are done
-    stage_rows<CB>(x, row0, n, D, S, s_rows, wide != 0, lane, wave);
-    const float F = eval_tile<split_terms(P), KIND, CB>(tp, s_rows, S, s_goff, s_ohp, s_z, s_red, lane, wave);
-    if (wave == 0 && lane < R && row0 + lane < n) out[row0 + lane] = F + static_cast<float>(tp.bias);
+    stage_rows(x, row0, n, D, S, s_rows, wide != 0, lane, wave);
+    const float F = eval_tile<NT, KIND, NT == 2 ? 4 : 3>(tp, s_rows, S, s_goff, s_ohp, s_ring, s_red, lane, wave);
+    if (wave == 0 && lane < kRows && row0 + lane < n) out[row0 + lane] = F + static_cast<float>(tp.bias);
   }
 }
 
@@ -460,21 +528,20 @@ struct CompDesc {
   TiledProb tp;
   int six;        // split mode: six products
   int unrotated;  // z = s (x - o_hi) + c' per variable, no rotation (no pair terms)
+  int index;      // the component's place in the composition (sigma, lambda, bias, G order)
 };
 
 // Unrotated component on the staged rows: each wave takes rows, lanes the variables; returns the
-// component value in wave 0 lanes < R (through s_red).
-template <int CB>
+// component value in wave 0 lanes < 32 (through s_red).
 __device__ __forceinline__ float eval_unrotated(const TiledProb &tp, const float *s_rows, int S, float *s_red, int lane,
                                                 int wave) {
-  constexpr int R = 16 * CB;
   const float s = static_cast<float>(tp.scale0);
   const float *oh = static_cast<const float *>(tp.oh);
   const float *czp = static_cast<const float *>(tp.cz);
   const float *cfp = static_cast<const float *>(tp.coef);
   const TiledSeg &sg = tp.segs[0];
   const float prm = seg_param(sg);
-  for (int rr = wave; rr < R; rr += kWaves) {
+  for (int rr = wave; rr < kRows; rr += kWaves) {
     Acc<float> m;
     m.init();
     for (int j0 = 0; j0 < tp.D; j0 += 64) {
@@ -515,33 +582,35 @@ __device__ __forceinline__ float eval_unrotated(const TiledProb &tp, const float
     }
   }
   __syncthreads();
-  const float F = (wave == 0 && lane < R) ? s_red[lane * kSlots] : 0.0f;
+  const float F = (wave == 0 && lane < kRows) ? s_red[lane * kSlots] : 0.0f;
   __syncthreads();
   return F;
 }
 
-// LDS carve of the fused composition: the row carve for the largest component tables, then the
-// component values (FP32) and squared distances (FP64) per (component, row).
+// LDS carve of the fused composition: the row carve for the largest component tables (ring for
+// six products), then the component values (FP32) and squared distances (FP64) per
+// (component, row).
 struct CompCarve {
   Carve base;
   int g, d2, total;
 };
-__host__ __device__ inline CompCarve comp_carve(int Dpmax, int S, int CB) {
+__host__ __device__ inline CompCarve comp_carve(int Dpmax, int S) {
   CompCarve c;
-  c.base = carve(Dpmax, S, CB, CB == 1);
-  const int R = 16 * CB;
+  c.base = carve(Dpmax, S, 3);
   c.g = c.base.total;
-  c.d2 = c.g + round16(8 * R * 4);
-  c.total = c.d2 + 8 * R * 8;
+  c.d2 = c.g + round16(8 * kRows * 4);
+  c.total = c.d2 + 8 * kRows * 8;
   return c;
 }
 
 // Composition (Sec. 6, Eqs. (composition) and (weight)) with every component on the same staged
-// rows: X is read from HBM once.  Per tile: each component's value G_i (its gather tables loaded
-// into LDS in turn, f_opt excluded), then d_i^2 = |x - o^i|^2 in FP64 from the staged FP32 rows,
-// log-domain weights in FP64 (one-hot where some d_i = 0), F = sum omega_i (lambda_i G_i + bias_i)
-// + f_opt.
-template <int CB>
+// rows: X is read from HBM once.  Per tile: d_i^2 = |x - o^i|^2 in FP64 from the staged FP32 rows
+// (before any component writes z over them), then each component's value G_i in the order of
+// comps (its gather tables loaded into LDS in turn, f_opt excluded; a component with pair terms,
+// which overwrites the rows, comes last), log-domain weights in FP64 (one-hot where some
+// d_i = 0), F = sum omega_i (lambda_i G_i + bias_i) + f_opt.
+// (A template so that the headers including this one define no kernel symbol of their own.)
+template <int NTMAX>
 __global__ __launch_bounds__(kThreads) void k_rowres_comp(const CompDesc *__restrict__ comps, int nc, int Dpmax,
                                                           int S, const float *__restrict__ x, int n, int D,
                                                           const double *__restrict__ o64,
@@ -549,41 +618,26 @@ __global__ __launch_bounds__(kThreads) void k_rowres_comp(const CompDesc *__rest
                                                           const double *__restrict__ lambda,
                                                           const double *__restrict__ bias, double fopt,
                                                           float *__restrict__ out, int wide) {
-  constexpr int R = 16 * CB;
   extern __shared__ __align__(16) unsigned char smem[];
-  const CompCarve L = comp_carve(Dpmax, S, CB);
+  static_assert(NTMAX == 3, "the composition ring holds six-product steps");
+  const CompCarve L = comp_carve(Dpmax, S);
   uint16_t *s_goff = reinterpret_cast<uint16_t *>(smem + L.base.goff);
   float *s_ohp = reinterpret_cast<float *>(smem + L.base.ohp);
   float *s_rows = reinterpret_cast<float *>(smem + L.base.rows);
-  float *s_z = reinterpret_cast<float *>(smem + L.base.zc);
+  unsigned char *s_ring = smem + L.base.ring;
   float *s_red = reinterpret_cast<float *>(smem + L.base.red);
   float *s_g = reinterpret_cast<float *>(smem + L.g);
   double *s_d2 = reinterpret_cast<double *>(smem + L.d2);
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (threadIdx.x < R) s_rows[threadIdx.x * S + D] = 0.0f;
-  const int ntiles = (n + R - 1) / R;
+  const int ntiles = (n + kRows - 1) / kRows;
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int row0 = tile * R;
+    const int row0 = tile * kRows;
     __syncthreads();
-    stage_rows<CB>(x, row0, n, D, S, s_rows, wide != 0, lane, wave);
-    for (int i = 0; i < nc; ++i) {
-      const CompDesc &cd = comps[i];
-      float G;
-      if (cd.unrotated) {
-        G = eval_unrotated<CB>(cd.tp, s_rows, S, s_red, lane, wave);
-      } else {
-        __syncthreads();  // the previous component's readers of the tables are done
-        load_tables(cd.tp, s_goff, s_ohp);
-        __syncthreads();
-        if (cd.six) G = eval_tile<3, -1, CB>(cd.tp, s_rows, S, s_goff, s_ohp, s_z, s_red, lane, wave);
-        else G = eval_tile<2, -1, CB>(cd.tp, s_rows, S, s_goff, s_ohp, s_z, s_red, lane, wave);
-      }
-      if (wave == 0 && lane < R) s_g[i * R + lane] = G;
-    }
+    stage_rows(x, row0, n, D, S, s_rows, wide != 0, lane, wave);
     // squared distances to every optimum in FP64 (the FP32 rows widen exactly): each wave takes
     // rows, lanes the variables
-    for (int rr = wave; rr < R; rr += kWaves) {
+    for (int rr = wave; rr < kRows; rr += kWaves) {
       for (int i = 0; i < nc; ++i) {
         double acc = 0.0;
         for (int j = lane; j < D; j += 64) {
@@ -592,25 +646,39 @@ __global__ __launch_bounds__(kThreads) void k_rowres_comp(const CompDesc *__rest
         }
 #pragma unroll
         for (int sh = 1; sh < 64; sh <<= 1) acc += __shfl_xor(acc, sh, 64);
-        if (lane == 0) s_d2[i * R + rr] = acc;
+        if (lane == 0) s_d2[i * kRows + rr] = acc;
       }
     }
+    for (int k = 0; k < nc; ++k) {
+      const CompDesc &cd = comps[k];
+      float G;
+      if (cd.unrotated) {
+        G = eval_unrotated(cd.tp, s_rows, S, s_red, lane, wave);
+      } else {
+        __syncthreads();  // the previous component's readers of the tables are done
+        load_tables(cd.tp, s_goff, s_ohp);
+        __syncthreads();
+        if (cd.six) G = eval_tile<3, -1, 2>(cd.tp, s_rows, S, s_goff, s_ohp, s_ring, s_red, lane, wave);
+        else G = eval_tile<2, -1, 3>(cd.tp, s_rows, S, s_goff, s_ohp, s_ring, s_red, lane, wave);
+      }
+      if (wave == 0 && lane < kRows) s_g[cd.index * kRows + lane] = G;
+    }
     __syncthreads();
-    if (wave == 0 && lane < R && row0 + lane < n) {
+    if (wave == 0 && lane < kRows && row0 + lane < n) {
       int nzero = 0;
       double amax = -1.0e308;
       for (int i = 0; i < nc; ++i) {
-        const double d2 = s_d2[i * R + lane];
+        const double d2 = s_d2[i * kRows + lane];
         if (d2 == 0.0) ++nzero;
         else amax = fmax(amax, -0.5 * log(d2) - d2 / (2.0 * D * sigma[i] * sigma[i]));
       }
       double wsum = 0.0, g = 0.0;
       for (int i = 0; i < nc; ++i) {
-        const double d2 = s_d2[i * R + lane];
+        const double d2 = s_d2[i * kRows + lane];
         const double w = nzero ? (d2 == 0.0 ? 1.0 : 0.0)
                                : exp(-0.5 * log(d2) - d2 / (2.0 * D * sigma[i] * sigma[i]) - amax);
         wsum += w;
-        g += w * (lambda[i] * static_cast<double>(s_g[i * R + lane]) + bias[i]);
+        g += w * (lambda[i] * static_cast<double>(s_g[i * kRows + lane]) + bias[i]);
       }
       out[row0 + lane] = static_cast<float>(g / wsum + fopt);
     }

@@ -62,6 +62,8 @@ struct TiledProb {
   int S;          // LDS row stride (floats) of the row-resident kernel
   int D, Dp, nblocks, ngroups, nsegs;
   int any_pairwise;
+  int pair_mtiles_max;  // m-tiles of the largest rotation block with pair terms (host use)
+  int qfrag_kib;        // size of the rotation tiles in KiB (host use)
   int rowwise;    // unrotated basic problem: z = s (x - o) + c' per variable, no MFMA work
   double scale0;  // s of that problem
   double bias;

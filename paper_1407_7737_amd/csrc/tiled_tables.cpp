@@ -1,5 +1,6 @@
 // tiled_tables.cpp -- host construction of the tiled path's device tables (basic functions of
 // any dimension, hybrid functions of Sec. 5).
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -207,6 +208,10 @@ hipError_t build_tiled(const Problem &p, int path, TiledDev &td, std::string &er
   tp.nsegs = nseg;
   tp.bias = p.fopt;
   tp.any_pairwise = 0;
+  tp.pair_mtiles_max = 0;
+  for (size_t b = 0; b < blocks.size(); ++b)
+    if (kind_is_pairwise(fn_spec(p.segs[hybrid ? blocks[b].seg : 0].base).kind))
+      tp.pair_mtiles_max = std::max(tp.pair_mtiles_max, ceil32(blocks[b].n) / 16);
   // unrotated basic problems: the identity blocks of 32 keep packed position = variable, and
   // the row-wise kernel reads the per-position tables by variable
   tp.rowwise = (!hybrid && !rotate) ? 1 : 0;
@@ -264,6 +269,7 @@ hipError_t build_tiled(const Problem &p, int path, TiledDev &td, std::string &er
   if ((e = up(coef.data(), coef.size(), &tp.coef)) != hipSuccess) return e;
   if ((e = up(succ.data(), succ.size() * 4, reinterpret_cast<const void **>(&tp.succ))) != hipSuccess) return e;
   if ((e = up(qfrag.data(), qfrag.size(), &tp.qfrag)) != hipSuccess) return e;
+  tp.qfrag_kib = static_cast<int>((qfrag.size() + 1023) / 1024);
   if ((e = up(blk4.data(), blk4.size() * 4, reinterpret_cast<const void **>(&tp.blocks))) != hipSuccess) return e;
   if ((e = up(grp4.data(), grp4.size() * 4, reinterpret_cast<const void **>(&tp.groups))) != hipSuccess) return e;
   if ((e = up(goff16.data(), goff16.size() * 2, reinterpret_cast<const void **>(&tp.goff))) != hipSuccess) return e;

@@ -220,13 +220,14 @@ def composition_allowance(orc, p, gids, x):
     return allow
 
 
-@pytest.mark.parametrize("dim", [10, 30, 100, 1000])
+@pytest.mark.parametrize("dim", [10, 30, 100, 200, 1000])
 def test_paper_compositions(env, dim):
     """The eight composition functions of Sec. 6 (ids 29-36), with their optimum at the origin
     for the third component; rows include points at and near every component optimum.  Every
     row meets the FP32 bar plus its own allowance for discontinuous components (Schwefel, also
     inside the hybrid components of ids 35-36) weighted by omega_i lambda_i; rows exactly at an
-    optimum (one-hot weights) meet the plain bar."""
+    optimum (one-hot weights) meet the plain bar.  D = 200 runs the fused composition kernel (all
+    components on the same staged rows), D = 1000 one row-resident launch per component."""
     c, orc, torch, use = env
     use(dim)
     from paper_1407_7737_amd.inputs import population, near
