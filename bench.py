@@ -63,6 +63,11 @@ KERNEL_SOURCES = ["eval_resident.h", "formulas.h", "devprob.h", "kernels.h"]
 COPY_PROBE_BYTES = N * DIM * 4  # the probe reads the FP32 population once and writes it once
 
 
+def progress(msg: str) -> None:
+    """A progress line on stderr (stdout carries only the result line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
@@ -217,6 +222,7 @@ def secondary(torch, c, reps: int = 10) -> dict:
     # D = 1000, N = 2^18: the same eight formulas on the tiled path, default split mode and the
     # plain FP32 mode
     d, n = 1000, 1 << 18
+    progress("secondary: D=1000, N=2^18")
     c.initialize(d, n, 0)
     try:
         x = torch.from_numpy(population(n, d, seed=0, dtype=np.float32)).to(dev)
@@ -246,6 +252,7 @@ def secondary(torch, c, reps: int = 10) -> dict:
                                 "sum_nk2": rotation_work(c, 11)[0]}
         del x
         # hybrid and composition at D = 1000, N = 16384
+        progress("secondary: hybrid and composition, D=1000, N=16384")
         m = 16384
         xh = torch.from_numpy(population(m, d, seed=1, dtype=np.float32)).to(dev)
         oh = torch.empty(m, dtype=torch.float32, device=dev)
@@ -271,6 +278,7 @@ def secondary(torch, c, reps: int = 10) -> dict:
     finally:
         c.dispose()
     # 64 batched populations
+    progress("secondary: 64 batched populations")
     c.initialize(10, 2048, 0)
     try:
         fids, dims, counts = batch_params(64, seed=0)
@@ -318,6 +326,7 @@ def secondary(torch, c, reps: int = 10) -> dict:
         finally:
             c.dispose()
     out["batch_64"]["one_call_per_population_ms"] = per_call
+    progress("secondary: 50-row latency and DE generations")
     out["latency_n50"] = latency_small(torch, c)
     out["de_n50"] = de_generations(torch, c)
     return out
@@ -460,10 +469,21 @@ FAMILY = {0: "wsphere", 5: "griewank", 6: "rastrigin", 9: "rosenbrock", 10: "sch
 PATH_NAME = {0: "x3 split", 1: "FP32", 2: "FP64", 3: "x6 split"}
 
 
-def trace_summary(kind: str, headline_dir: str, secondary_dir: str) -> None:
-    """Per-kernel launch durations from the run_kernel_stats.csv of two rocprofv3 --kernel-trace
-    --stats runs of this script (the headline step, then the run with the secondary workloads);
-    writes profiles/resident_d100_n262144_kernel_trace.txt and profiles/secondary_kernel_trace.txt."""
+def trace_summary(kind: str, headline_dir: str, secondary_dir: str, steps: int = 5) -> None:
+    """Per-kernel launch durations from two rocprofv3 --kernel-trace --stats runs of this script
+    (the headline step, then the run with the secondary workloads); writes
+    profiles/resident_d100_n262144_kernel_trace.txt and profiles/secondary_kernel_trace.txt.
+    The headline table averages the last 2 * steps dispatches of each kernel (the timed steps
+    back to back, then the event-bracketed ones), read from the per-dispatch trace: the
+    autotuner's trial launches of the same kernels come first."""
+    def dispatches(d):
+        files = glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True)
+        rows = []
+        for f in files:
+            rows.extend(csv.DictReader(open(f)))
+        rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+        return rows
+
     def stats(d):
         f = os.path.join(d, "run_kernel_stats.csv")
         return list(csv.DictReader(open(f)))
@@ -476,33 +496,37 @@ def trace_summary(kind: str, headline_dir: str, secondary_dir: str) -> None:
         return m.group(1) if m else None
 
     cmd_head = ("rocprofv3 --kernel-trace --stats --output-format csv -d <OUT> -o run -- python -u bench.py "
-                "--steps 5 --warmup 1 --no-cpu-baseline --no-secondary")
+                f"--steps {steps} --warmup 1 --no-cpu-baseline --no-secondary")
     cmd_sec = ("rocprofv3 --kernel-trace --stats --output-format csv -d <OUT2> -o run -- python -u bench.py "
                "--steps 2 --warmup 1 --no-cpu-baseline")
-    summ = "python bench.py --trace-summary <OUT> <OUT2>"
+    summ = f"python bench.py --trace-summary <OUT> <OUT2>{'' if steps == 5 else f' --trace-steps {steps}'}"
     lines = ["Kernel durations, D=100, N=2^18 (bench step: 8 formulas, split path then FP64 path)", "",
              "commands (repository root):", "  " + cmd_head, "  " + summ,
-             "source: <OUT>/run_kernel_stats.csv (11 launches per kernel: 1 warmup, 5 timed steps back to",
-             "back, then 5 steps with each launch between two HIP events for the per-launch durations).",
+             f"source: <OUT>/run_kernel_trace.csv: per kernel the last {2 * steps} dispatches ({steps} timed steps back",
+             f"to back, then {steps} steps with each launch between two HIP events, as bench.py times them); the",
+             "autotuner's trial launches and the warmup come before them and are not counted.",
              "k_eval_resident<path, family, rotated, vec>: path 0 = split BF16x3, 3 = split BF16x6, 2 = FP64;",
              "families 0 weighted sphere, 5 Griewank, 6 Rastrigin, 9 Rosenbrock, 10 Schwefel, 13 Ackley.", "",
              f"{'kernel':28s} {'path':9s} {'family':11s} {'rot':>3s} {'calls':>5s} {'avg us':>8s} {'min us':>8s} {'max us':>8s}"]
+    per = {}
+    for r in dispatches(headline_dir):
+        k = short(r["Kernel_Name"])
+        if k and k.startswith("k_eval_resident<"):
+            per.setdefault(k, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
     rows = []
-    for r in stats(headline_dir):
-        k = short(r["Name"])
-        if not k or not k.startswith("k_eval_resident<"):
-            continue
+    for k, durs in per.items():
+        d = durs[-2 * steps:]
         pth, fam, rot, _ = (int(v) for v in k[len("k_eval_resident<"):-1].split(","))
-        rows.append((float(r["AverageNs"]), k, pth, fam, rot, int(r["Calls"]), float(r["MinNs"]), float(r["MaxNs"])))
+        rows.append((float(np.mean(d)), k, pth, fam, rot, len(d), min(d), max(d)))
     for avg, k, pth, fam, rot, calls, mn, mx in sorted(rows, reverse=True):
         lines.append(f"{k:28s} {PATH_NAME[pth]:9s} {FAMILY.get(fam, str(fam)):11s} {rot:3d} {calls:5d} "
-                     f"{avg / 1e3:8.2f} {mn / 1e3:8.2f} {mx / 1e3:8.2f}")
+                     f"{avg:8.2f} {mn:8.2f} {mx:8.2f}")
     with open(os.path.join(ROOT, "profiles", "resident_d100_n262144_kernel_trace.txt"), "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))
-    lines = ["Kernel durations of the secondary workloads (bench.py --steps 2): D=1000 N=2^18 eight formulas",
-             "(four 65536-row passes each), hybrid and composition at D=1000 N=16384, the 64-population batch",
-             "(tuning included), 50-row latency calls; the D=100 resident kernels of the headline step as well.", "",
+    lines = ["Kernel durations of the secondary workloads (bench.py --steps 2): D=1000 N=2^18 eight formulas,",
+             "hybrid and composition at D=1000 N=16384, the 64-population batch (tuning included), 50-row",
+             "latency calls, DE generations; the D=100 resident kernels of the headline step as well.", "",
              "commands (repository root):", "  " + cmd_sec, "  " + summ,
              "source: <OUT2>/run_kernel_stats.csv; every launch of the run is counted (calls include warmups and tuning).",
              "", f"{'kernel':60s} {'calls':>7s} {'avg us':>9s} {'total ms':>9s}"]
@@ -687,6 +711,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the built-in launch-shape heuristic")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--trace-summary", nargs=2, metavar=("HEADLINE_DIR", "SECONDARY_DIR"))
+    ap.add_argument("--trace-steps", type=int, default=5, help="--steps of the profiled headline run")
     ap.add_argument("--sq-summary", nargs=2, metavar=("P1_DIR", "P2_DIR"))
     ap.add_argument("--profile-d1000", action="store_true", help="run only the D=1000 workloads (for rocprofv3)")
     ap.add_argument("--tiled-summary", nargs=5, metavar=("TRACE", "FETCH", "WRITE", "SQ1", "SQ2"))
@@ -698,7 +723,7 @@ def main():
         pmc_summary(*args.pmc_summary)
         return
     if args.trace_summary:
-        trace_summary("all", *args.trace_summary)
+        trace_summary("all", *args.trace_summary, steps=args.trace_steps)
         return
     if args.sq_summary:
         sq_summary(*args.sq_summary)
@@ -729,6 +754,7 @@ def main():
     # search log goes into the result line)
     tuning = {}
     if not args.no_tune:
+        progress("autotuning the launch shapes")
         for fid in FIDS:
             t = c.tune(fid, x32, fp64=False, reps=5)
             t64 = c.tune(fid, x64, fp64=True, reps=3)
@@ -767,7 +793,9 @@ def main():
         per = {fid: float(np.mean([a.elapsed_time(b) for a, b in ev[fid]])) for fid in FIDS}
         return wall, per
 
+    progress("timing the split path")
     wall32, per32 = timed(False)
+    progress("timing the FP64 path")
     wall64, per64 = timed(True)
     # the plain FP32 mode (FP32 matrix products) on the same points, per formula
     c.set_mode(c.MODE_FP32)
@@ -835,9 +863,11 @@ def main():
         "paper_context": PAPER_CONTEXT,
     }
     if not args.no_secondary:
+        progress("secondary workloads")
         res["secondary"] = secondary(torch, c)
     if not args.no_cpu_baseline:
         gpu = {fid: (outs32[fid].cpu().numpy(), outs64[fid].cpu().numpy()) for fid in FIDS}
+        progress("CPU oracle baseline")
         res["cpu_baseline"] = cpu_baseline(x32h, gpu)
     print(json.dumps(res), flush=True)
 

@@ -120,19 +120,21 @@ __device__ __forceinline__ T t_abs(T v) {
   if constexpr (sizeof(T) == 4) return __builtin_fabsf(v); else return __builtin_fabs(v);
 }
 
-// One Schwefel term 418.9829 - g1(w) of Eq. (basic_schwefel), branch free, on w = z +
-// 420.9687... (the tables fold the constant into c').  With a = |w|: for a <= 500 g1 is
-// w sin(sqrt a); beyond, both outer branches fold a back to u = 500 - mod(a, 500) and subtract
-// (a - 500)^2 / (10000 n): g1 = sign(w) u sin(sqrt u) - penalty.  Summing 418.9829 - g1 per
-// term (the function is the sum of these) keeps the terms small near the optimum, where
-// 418.9829 n and the sum of g1 would cancel to the ulp of 418.9829 n.  In FP32 the constant is
-// fl32(418.9829), the finalisation adds n (418.9829 - fl32(418.9829)), and within |z| < 6 of the
-// optimum (z = w - 420.9687...) the term comes from the fitted series of schwefel_series.h.
+// One Schwefel term 418.9829 - g1(z + w*) of Eq. (basic_schwefel), branch free, w* =
+// 420.9687....  With w = z + w* and a = |w|: for a <= 500 g1 is w sin(sqrt a); beyond, both outer
+// branches fold a back to u = 500 - mod(a, 500) and subtract (a - 500)^2 / (10000 n):
+// g1 = sign(w) u sin(sqrt u) - penalty.  Summing 418.9829 - g1 per term (the function is the sum
+// of these) keeps the terms small near the optimum, where 418.9829 n and the sum of g1 would cancel
+// to the ulp of 418.9829 n.  In FP32 the constant is fl32(418.9829), the finalisation adds
+// n (418.9829 - fl32(418.9829)), and within |z| < 4 of the optimum the term comes from the fitted
+// series of schwefel_series.h: every term of a row at the optimum shares one argument, so the
+// direct form's roundings of sqrt, phase and sine (~4e-5 per term) would add up over the row.
 template <typename T>
-__device__ __forceinline__ T schwefel_g1(T w, T inv10000n) {
-  const T a = t_abs(w);
-  const bool far = a > T(500);
+__device__ __forceinline__ T schwefel_g1(T z, T inv10000n) {
   if constexpr (sizeof(T) == 4) {
+    const float w = z + static_cast<float>(kSchwefelW);
+    const float a = __builtin_fabsf(w);
+    const bool far = a > 500.0f;
     // mod(a, 500) as 500 fract(a / 500): a few ulps of a from the exact remainder, which
     // only moves the jumps at a = 1000, 1500, ... by as much
     const float m = 500.0f * __builtin_amdgcn_fractf(a * 0.002f);
@@ -144,20 +146,16 @@ __device__ __forceinline__ T schwefel_g1(T w, T inv10000n) {
     const float sn = __builtin_amdgcn_sinf(__builtin_amdgcn_sqrtf(u) * 0.15915494309189535f);
     // C - g1 with the product rounded once
     const float direct = __builtin_fmaf(-__builtin_copysignf(u, w), sn, static_cast<float>(kSchwefelC)) + d * d * inv10000n;
-    // near the optimum of g1 (|z| < rho, z = w - w*: exact up to the rounding of w, whose effect
-    // on the term is second order there) the fitted series T0 + z^2 Q(z / rho): every term of a
-    // row at the optimum shares one argument, so the direct form's roundings of sqrt, phase and
-    // sine (~4e-5 per term) would add up over the row
-    constexpr float kW = static_cast<float>(kind_zshift(K_SCHWEFEL));
-    constexpr float kWErr = static_cast<float>(static_cast<double>(kW) - kind_zshift(K_SCHWEFEL));
-    const float z = (w - kW) + kWErr;
     const float t = z * kSchwefelInvRho;
-    float q = kSchwefelQ[5];
+    float q = kSchwefelQ[3];
 #pragma unroll
-    for (int j = 4; j >= 0; --j) q = __builtin_fmaf(q, t, kSchwefelQ[j]);
+    for (int j = 2; j >= 0; --j) q = __builtin_fmaf(q, t, kSchwefelQ[j]);
     const float series = __builtin_fmaf(z * z, q, kSchwefelT0);
     return __builtin_fabsf(z) < kSchwefelRho ? series : direct;
   } else {
+    const T w = z + T(kSchwefelW);
+    const T a = t_abs(w);
+    const bool far = a > T(500);
     T m = a - T(500) * t_floor(a * T(0.002));  // mod(a, 500); the floor may be off by one
     m = m < T(0) ? m + T(500) : m;
     m = m >= T(500) ? m - T(500) : m;
@@ -243,7 +241,7 @@ __device__ __forceinline__ void phi(T (&v)[3], T &p, T z, T zn, T coef, T prm) {
     const T e = z - T(1);
     v[0] += T(100) * d * d + e * e;
   } else if constexpr (KIND == K_SCHWEFEL) {
-    v[0] += schwefel_g1(z, prm);  // z carries the 420.9687... offset: w
+    v[0] += schwefel_g1(z, prm);
   } else if constexpr (KIND == K_KATSUURA) {
     T t = T(0), pj = T(1);
 #pragma unroll 4

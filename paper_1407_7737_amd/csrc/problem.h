@@ -32,12 +32,14 @@ enum Kind : int {
 };
 
 // Constant added to z before a family's terms, folded into the c' tables (constexpr: usable in
-// device code too): Schwefel's g1 takes w = z + 420.9687462275036 (Sec. 4.9); HappyCat and HGBat
-// (Secs. 4.14-4.15) take w = z + 1, since their optimum sits at z = -1 and terms written in w keep
-// their precision as w -> 0, where terms written in z ~ -1 cancel.
-constexpr double kind_zshift(int kind) {
-  return kind == K_SCHWEFEL ? 420.9687462275036 : (kind == K_HAPPYCAT || kind == K_HGBAT) ? 1.0 : 0.0;
-}
+// device code too): HappyCat and HGBat (Secs. 4.14-4.15) take w = z + 1, since their optimum sits
+// at z = -1 and terms written in w keep their precision as w -> 0, where terms written in z ~ -1
+// cancel.  (Schwefel's g1 takes z + 420.9687462275036 too, but adds it in the formula, which
+// needs z itself near the optimum.)
+constexpr double kind_zshift(int kind) { return (kind == K_HAPPYCAT || kind == K_HGBAT) ? 1.0 : 0.0; }
+
+// Schwefel's g1 argument offset w* = 420.9687462275036 (Sec. 4.9).
+constexpr double kSchwefelW = 420.9687462275036;
 
 // Schwefel's constant 418.9829, kept as printed (Sec. 4.9).
 constexpr double kSchwefelC = 418.9829;

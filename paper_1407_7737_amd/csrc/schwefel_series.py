@@ -20,8 +20,8 @@ import numpy as np
 W_OPT = 420.9687462275036  # Sec. 4.9
 C_SCHWEFEL = 418.9829      # Sec. 4.9
 C_F32 = float(np.float32(C_SCHWEFEL))  # the constant as the FP32 kernels hold it
-RHO = 6.0                  # |z| below which the polynomial is used
-DEGREE = 5                 # degree of Q
+RHO = 4.0                  # |z| below which the polynomial is used
+DEGREE = 3                 # degree of Q
 NODES = 400
 
 HERE = os.path.dirname(os.path.abspath(__file__))

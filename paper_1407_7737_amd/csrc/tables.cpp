@@ -10,6 +10,8 @@
 #include <cstring>
 
 #include "kernels.h"
+#include "problem.h"
+#include "schwefel_series.h"
 
 namespace curob {
 
@@ -32,6 +34,11 @@ float bf16_bits_to_float(uint16_t h) {
   float f;
   std::memcpy(&f, &u, 4);
   return f;
+}
+
+double schwefel_pad_term(bool f64) {
+  if (!f64) return static_cast<double>(kSchwefelT0);
+  return kSchwefelC - kSchwefelW * std::sin(std::sqrt(kSchwefelW));
 }
 
 int lds_stride(int D, int m) {
@@ -290,7 +297,7 @@ bool build_host_tables(const Problem &p, int path, HostTables &ht, std::string &
   if (kind == K_WEIERSTRASS) pb.padc[0] = npad * (2.0 - 9.5367431640625e-07);   // sum_k a^k cos(0)
   if (kind == K_ACKLEY) pb.padc[1] = npad;                                          // cos(0) = 1
   if (kind == K_HGBAT) pb.padc[1] = 2.0 * npad;                                     // (0 - 1)(0 - 2)
-  if (kind == K_SCHWEFEL) pb.padc[0] = npad * (f64 ? kSchwefelC : static_cast<double>(static_cast<float>(kSchwefelC)));
+  if (kind == K_SCHWEFEL) pb.padc[0] = npad * schwefel_pad_term(f64);  // z = 0: the term at the optimum
   if (kind == K_LUNACEK) {
     pb.padc[0] = 6.25 * npad;  // (0 - 2.5)^2
     pb.padc[1] = 6.25 * npad;  // (0 + 2.5)^2

@@ -44,4 +44,8 @@ float bf16_bits_to_float(uint16_t h);
 // banks), m the padded position count.
 int lds_stride(int D, int m);
 
+// What one padded Schwefel position (z = 0, the optimum of g1) adds to the row sum of terms
+// 418.9829 - g1: on the FP32 paths the series value at 0, on the FP64 path the term itself.
+double schwefel_pad_term(bool f64);
+
 }  // namespace curob

@@ -245,7 +245,7 @@ hipError_t build_tiled(const Problem &p, int path, TiledDev &td, std::string &er
     if (ts.kind == K_WEIERSTRASS) ts.padc[0] = npad * (2.0 - 9.5367431640625e-07);
     if (ts.kind == K_ACKLEY) ts.padc[1] = npad;
     if (ts.kind == K_HGBAT) ts.padc[1] = 2.0 * npad;
-    if (ts.kind == K_SCHWEFEL) ts.padc[0] = npad * (f64 ? kSchwefelC : static_cast<double>(static_cast<float>(kSchwefelC)));
+    if (ts.kind == K_SCHWEFEL) ts.padc[0] = npad * schwefel_pad_term(f64);
     if (ts.kind == K_LUNACEK) {
       ts.padc[0] = 6.25 * npad;
       ts.padc[1] = 6.25 * npad;
