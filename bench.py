@@ -627,15 +627,10 @@ def profile_d1000(torch, c, reps: int = 3) -> None:
 
 def tiled_summary(trace_dir: str, fetch_dir: str, write_dir: str, sq1_dir: str, sq2_dir: str) -> None:
     """Per-kernel durations, HBM traffic and SQ counters of the D = 1000 workloads from five
-    rocprofv3 runs of `bench.py --profile-d1000`; writes profiles/tiled_d1000_kernels.txt."""
-    def counters(d):
-        vals = {}
-        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
-            for row in csv.DictReader(open(f)):
-                vals.setdefault(row["Kernel_Name"], {}).setdefault(row["Counter_Name"], []).append(
-                    float(row["Counter_Value"]))
-        return vals
-
+    rocprofv3 runs of `bench.py --profile-d1000`; writes profiles/tiled_d1000_kernels.txt.  The
+    dispatches of each run are taken in order and labelled by workload (the eight formulas,
+    three launches each, then the hybrid, then the composition, then the copy probe), so the
+    component launches of the composition are not mixed with the formulas' launches."""
     def short(name):
         m = re.search(r"(k_\w+)<([^>]*)>", name)
         if m:
@@ -646,24 +641,51 @@ def tiled_summary(trace_dir: str, fetch_dir: str, write_dir: str, sq1_dir: str, 
         m = re.search(r"(k_\w+)", name)
         return m.group(1) if m else ("neg" if "neg" in name.lower() else None)
 
-    dur = {}
-    for r in csv.DictReader(open(os.path.join(trace_dir, "run_kernel_stats.csv"))):
-        k = short(r["Name"])
-        if k:
-            a = dur.setdefault(k, [0, 0.0])
-            a[0] += int(r["Calls"])
-            a[1] += float(r["TotalDurationNs"])
-    merged = {}
-    for d in (fetch_dir, write_dir, sq1_dir, sq2_dir):
-        for name, cs in counters(d).items():
-            k = short(name)
-            if k:
-                for cn, v in cs.items():
-                    merged.setdefault(k, {}).setdefault(cn, []).extend(v)
-    med = {k: {cn: float(np.median(v)) for cn, v in cs.items()} for k, cs in merged.items()}
+    def label(seq):
+        """Workload label per dispatch, from the order profile_d1000 launches them in."""
+        out, i = [], 0
+        for fid in FIDS:
+            for _ in range(3):
+                out.append(NAMES[fid])
+        i = len(out)
+        rest = len(seq) - i
+        nprobe = sum(1 for k in seq if k == "neg")
+        body = rest - nprobe
+        out.extend(["hybrid"] * 3)
+        out.extend(["composition"] * (body - 3))
+        out.extend(["copy probe"] * nprobe)
+        return out[:len(seq)]
+
+    def dispatches(d, with_counters):
+        rows = {}
+        pat = "*counter_collection.csv" if with_counters else "*kernel_trace.csv"
+        for f in glob.glob(os.path.join(d, "**", pat), recursive=True):
+            for r in csv.DictReader(open(f)):
+                k = short(r["Kernel_Name"])
+                if not k:
+                    continue
+                e = rows.setdefault(int(r["Dispatch_Id"]), {"kernel": k})
+                if with_counters:
+                    e[r["Counter_Name"]] = e.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+                else:
+                    e["us"] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        seq = [rows[i] for i in sorted(rows)]
+        for e, lab in zip(seq, label([e["kernel"] for e in seq])):
+            e["workload"] = lab
+        return seq
+
+    groups = {}
+    for d, wc in ((trace_dir, False), (fetch_dir, True), (write_dir, True), (sq1_dir, True), (sq2_dir, True)):
+        for e in dispatches(d, wc):
+            g = groups.setdefault((e["workload"], e["kernel"]), {})
+            for cn, v in e.items():
+                if cn not in ("kernel", "workload"):
+                    g.setdefault(cn, []).append(v)
+    med = {k: {cn: float(np.median(v)) for cn, v in cs.items()} for k, cs in groups.items()}
     probe = PROFILE_ROWS * 1000 * 4
-    cf = probe / (med["neg"]["FETCH_SIZE"] * 1024.0)
-    cw = probe / (med["neg"]["WRITE_SIZE"] * 1024.0)
+    neg = med[("copy probe", "neg")]
+    cf = probe / (neg["FETCH_SIZE"] * 1024.0)
+    cw = probe / (neg["WRITE_SIZE"] * 1024.0)
     simds, xcds = 1024, 8
     lines = ["D=1000 workloads: per-kernel duration, HBM traffic and SQ counters (rocprofv3, five runs)", "",
              "commands (repository root):",
@@ -675,16 +697,19 @@ def tiled_summary(trace_dir: str, fetch_dir: str, write_dir: str, sq1_dir: str, 
              "  rocprofv3 --pmc SQ_INSTS_MFMA SQ_VALU_MFMA_BUSY_CYCLES SQ_WAIT_ANY SQ_ACTIVE_INST_ANY SQ_INSTS_VMEM_RD "
              "SQ_WAIT_INST_LDS GRBM_GUI_ACTIVE --output-format csv -d <S2> -- python -u bench.py --profile-d1000",
              "  python bench.py --tiled-summary <T> <F> <W> <S1> <S2>", "",
-             f"Workload: the eight formulas on one 65536-row pass at D=1000 (default split mode), the hybrid and",
-             f"the composition at N=16384; 3 launches each.  Bytes: FETCH_SIZE/WRITE_SIZE (KiB per dispatch) scaled",
-             f"by the copy probe (torch.neg of {probe} bytes read and written): fetch x{cf:.3f}, write x{cw:.3f}.",
-             "Algorithmic bytes of the method per 65536-row pass: X read once, 262.1 MB, plus 0.26 MB written.",
-             "MFMA%: SQ_VALU_MFMA_BUSY_CYCLES / (1024 SIMDs x GRBM_GUI_ACTIVE/8).", "",
-             f"{'kernel':34s} {'calls':>5s} {'avg us':>8s} {'read MB':>8s} {'write MB':>9s} {'MFMA%':>6s} "
+             "Workload: the eight formulas on one 65536-row pass at D=1000 (default split mode), 3 launches each;",
+             "the hybrid and the composition (one launch per component plus the blend) at N=16384, 3 calls each.",
+             f"Bytes: FETCH_SIZE/WRITE_SIZE (KiB per dispatch, summed over dies) scaled by the copy probe (torch.neg",
+             f"of {probe} bytes read and written): fetch x{cf:.3f}, write x{cw:.3f}.  Algorithmic bytes per",
+             "65536-row pass: X read once, 262.1 MB, plus 0.26 MB written (N=16384: 65.5 MB).  A read below the",
+             "algorithmic figure is X partly served from the MALL (the three launches read the same rows).",
+             "MFMA%: SQ_VALU_MFMA_BUSY_CYCLES / (1024 SIMDs x GRBM_GUI_ACTIVE/8).  Per-wave counts: per launch.", "",
+             f"{'workload':12s} {'kernel':18s} {'n':>3s} {'avg us':>8s} {'read MB':>8s} {'write MB':>8s} {'MFMA%':>6s} "
              f"{'VALU/wave':>9s} {'LDS/wave':>8s} {'LDScf%':>6s} {'wait%':>6s}"]
-    for k in sorted(dur, key=lambda k: -dur[k][1]):
-        calls, tot = dur[k]
-        v = med.get(k, {})
+    order = {n: i for i, n in enumerate([NAMES[f] for f in FIDS] + ["hybrid", "composition", "copy probe"])}
+    for (wl, k) in sorted(med, key=lambda t: (order.get(t[0], 99), t[1])):
+        v = med[(wl, k)]
+        n = len(groups[(wl, k)].get("us", []))
         cyc = v.get("GRBM_GUI_ACTIVE", 0.0) / xcds
         waves = max(v.get("SQ_WAVES", 1.0), 1.0)
         rd = v.get("FETCH_SIZE", float("nan")) * 1024 * cf / 1e6
@@ -692,7 +717,7 @@ def tiled_summary(trace_dir: str, fetch_dir: str, write_dir: str, sq1_dir: str, 
         mf = 100 * v.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) / (simds * cyc) if cyc > 0 else float("nan")
         lc = 100 * v.get("SQ_LDS_BANK_CONFLICT", 0.0) / 256 / cyc if cyc > 0 else float("nan")
         wt = 100 * v.get("SQ_WAIT_ANY", 0.0) / max(v.get("SQ_WAVE_CYCLES", 1.0), 1.0)
-        lines.append(f"{k[:34]:34s} {calls:5d} {tot / calls / 1e3:8.2f} {rd:8.1f} {wr:9.1f} {mf:6.1f} "
+        lines.append(f"{wl[:12]:12s} {k[:18]:18s} {n:3d} {v.get('us', float('nan')):8.2f} {rd:8.1f} {wr:8.1f} {mf:6.1f} "
                      f"{v.get('SQ_INSTS_VALU', 0.0) / waves:9.0f} {v.get('SQ_INSTS_LDS', 0.0) / waves:8.0f} "
                      f"{lc:6.1f} {wt:6.1f}")
     with open(os.path.join(ROOT, "profiles", "tiled_d1000_kernels.txt"), "w") as f:
