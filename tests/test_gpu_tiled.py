@@ -431,3 +431,47 @@ def test_weierstrass_component_without_bias(env, dim):
             f"(bound {bound.min():.2e}..{bound.max():.2e}), mean {mean:.2e} +- {se:.2e}")
         assert np.all(np.abs(d) <= TOL32 * np.maximum(1.0, np.abs(ref32)) + bound), (m, float(np.abs(d).max()))
         assert abs(mean) <= 4.0 * se + 1e-6, (m, mean, se)
+
+
+@pytest.mark.parametrize("dim,bases,props", [
+    (1000, [14, 0, 11], [0.30, 0.35, 0.35]),   # Rosenbrock group of 300: z written over the staged rows
+    (1000, [14, 11], [0.60, 0.40]),            # Rosenbrock group of 600: too large for one pass, tiled kernels
+    (600, [22, 13, 16, 2], [0.25, 0.25, 0.25, 0.25]),  # four groups, two with pair terms (wrapping)
+])
+def test_hybrid_pair_groups(env, dim, bases, props):
+    """Hybrids whose groups have pair terms (Sec. 5): on the split paths the row-resident kernel
+    writes z of such a group back over the group's own x in LDS and sums the pair terms after
+    the last group, which needs the group in one pass of the kernel's m-tiles; a larger group
+    goes to the tiled kernels.  Both routes, every mode, every row against the oracle."""
+    c, orc, torch, use = env
+    use(dim)
+    from paper_1407_7737_amd.inputs import population, near
+    c.define_hybrid(101, bases, props)
+    p = orc.hybrid(101, dim, SEED, bases, props)
+    x = population(160, dim, seed=7)
+    x[:8] = near(np.repeat(p.shift()[None, :], 8, axis=0), 0.5, seed=8)
+    x[8] = p.shift()
+    x32w, f64, f = run_paths(c, torch, 101, x, all_modes(c))
+    assert rel_err(f64, p(x, threads=16)).max() <= TOL64
+    ref32 = p(x32w, threads=16)
+    allow = hybrid_allowance(orc, p, bases, x32w)
+    for m in f:
+        say(f"[hybrid-pairs] dim={dim} bases={bases} mode={m} max {check32(f[m], ref32, allow, (m, dim, bases)):.3e}")
+
+
+def test_beyond_row_resident_dimension(env):
+    """D = 1100 is past the row-resident kernel's LDS budget (32 rows of 1100 floats plus its
+    tables): the split modes take the tiled kernels there.  A rotated formula without and one
+    with pair terms, every mode, against the oracle."""
+    c, orc, torch, use = env
+    use(1100)
+    from paper_1407_7737_amd.inputs import population
+    x = population(96, 1100, seed=9)
+    for fid in (11, 14):
+        p = orc.basic(fid, 1100, SEED)
+        x32w, f64, f = run_paths(c, torch, fid, x, all_modes(c))
+        assert rel_err(f64, p(x, threads=16)).max() <= TOL64
+        ref32 = p(x32w, threads=16)
+        allow = basic_allowance(orc, fid, p.shift(), p.rotation(), x32w)
+        for m in f:
+            say(f"[d1100] fid={fid} mode={m} max {check32(f[m], ref32, allow, (m, fid)):.3e}")
