@@ -594,20 +594,26 @@ def sq_summary(p1_dir: str, p2_dir: str) -> None:
 PROFILE_ROWS = 1 << 16  # one pass of the tiled path
 
 
+PROFILE_PHASES = ["formulas", "hybrid", "composition", "fp32 mode", "copy probe"]
+
+
 def profile_d1000(torch, c, reps: int = 3) -> None:
     """The D = 1000 workloads alone, for rocprofv3 runs: the eight formulas on one 65536-row
-    pass (default split mode), the hybrid and the composition at N = 16384, `reps` launches
-    each, then the copy probe (torch.neg over the 65536-row population) that scales the
-    byte counters."""
+    pass (default split mode), the hybrid and the composition at N = 16384, rotated Rastrigin
+    and Rosenbrock in the FP32-MFMA mode (the tiled kernels), `reps` launches each, then the copy
+    probe (torch.neg over the 65536-row population) that scales the byte counters.  A one-element
+    torch.abs marks the end of each phase in the dispatch sequence."""
     from paper_1407_7737_amd.inputs import composition_params, hybrid_params, population
     d, n, m = 1000, PROFILE_ROWS, 16384
     c.initialize(d, n, 0)
+    marker = torch.zeros(1, device="cuda")
     try:
         x = torch.from_numpy(population(n, d, seed=0, dtype=np.float32)).cuda()
         o = torch.empty(n, dtype=torch.float32, device="cuda")
         for fid in FIDS:
             for _ in range(reps):
                 c.func_evaluatef(fid, x, out=o)
+        torch.abs(marker)
         bases, props = hybrid_params(d, seed=0)
         c.define_hybrid(100, bases, props)
         cb, sig, lam, bias = composition_params(seed=0)
@@ -615,6 +621,13 @@ def profile_d1000(torch, c, reps: int = 3) -> None:
         for pid in (100, 101):
             for _ in range(reps):
                 c.func_evaluatef(pid, x[:m], out=o[:m])
+            torch.abs(marker)
+        c.set_mode(c.MODE_FP32)
+        for fid in (11, 14):
+            for _ in range(reps):
+                c.func_evaluatef(fid, x, out=o)
+        c.set_mode(c.MODE_SPLIT)
+        torch.abs(marker)
         torch.cuda.synchronize()
         buf = torch.empty_like(x)
         for _ in range(reps):
@@ -639,22 +652,26 @@ def tiled_summary(trace_dir: str, fetch_dir: str, write_dir: str, sq1_dir: str, 
         if m:
             return m.group(1) + "<" + ",".join(m.groups()[1:]) + ">"
         m = re.search(r"(k_\w+)", name)
-        return m.group(1) if m else ("neg" if "neg" in name.lower() else None)
+        if m:
+            return m.group(1)
+        low = name.lower()
+        return "neg" if "neg" in low else ("marker" if "abs" in low else None)
 
     def label(seq):
-        """Workload label per dispatch, from the order profile_d1000 launches them in."""
-        out, i = [], 0
-        for fid in FIDS:
-            for _ in range(3):
-                out.append(NAMES[fid])
-        i = len(out)
-        rest = len(seq) - i
-        nprobe = sum(1 for k in seq if k == "neg")
-        body = rest - nprobe
-        out.extend(["hybrid"] * 3)
-        out.extend(["composition"] * (body - 3))
-        out.extend(["copy probe"] * nprobe)
-        return out[:len(seq)]
+        """Workload label per dispatch: phases end at the torch.abs markers profile_d1000 puts
+        between them; in the first phase each formula has its three launches, in FIDS order."""
+        out, phase, k = [], 0, 0
+        for name in seq:
+            if name == "marker":
+                out.append(None)
+                phase += 1
+                continue
+            if phase == 0:
+                out.append(NAMES[FIDS[min(k // 3, len(FIDS) - 1)]])
+                k += 1
+            else:
+                out.append(PROFILE_PHASES[min(phase, len(PROFILE_PHASES) - 1)])
+        return out
 
     def dispatches(d, with_counters):
         rows = {}
@@ -672,7 +689,7 @@ def tiled_summary(trace_dir: str, fetch_dir: str, write_dir: str, sq1_dir: str, 
         seq = [rows[i] for i in sorted(rows)]
         for e, lab in zip(seq, label([e["kernel"] for e in seq])):
             e["workload"] = lab
-        return seq
+        return [e for e in seq if e["workload"] is not None]
 
     groups = {}
     for d, wc in ((trace_dir, False), (fetch_dir, True), (write_dir, True), (sq1_dir, True), (sq2_dir, True)):
@@ -698,7 +715,8 @@ def tiled_summary(trace_dir: str, fetch_dir: str, write_dir: str, sq1_dir: str, 
              "SQ_WAIT_INST_LDS GRBM_GUI_ACTIVE --output-format csv -d <S2> -- python -u bench.py --profile-d1000",
              "  python bench.py --tiled-summary <T> <F> <W> <S1> <S2>", "",
              "Workload: the eight formulas on one 65536-row pass at D=1000 (default split mode), 3 launches each;",
-             "the hybrid and the composition (one launch per component plus the blend) at N=16384, 3 calls each.",
+             "the hybrid and the composition (one launch per component plus the blend) at N=16384, 3 calls each;",
+             "rotated Rastrigin and Rosenbrock in the FP32-MFMA mode (pack, tiled GEMM, finalize), 3 calls each.",
              f"Bytes: FETCH_SIZE/WRITE_SIZE (KiB per dispatch, summed over dies) scaled by the copy probe (torch.neg",
              f"of {probe} bytes read and written): fetch x{cf:.3f}, write x{cw:.3f}.  Algorithmic bytes per",
              "65536-row pass: X read once, 262.1 MB, plus 0.26 MB written (N=16384: 65.5 MB).  A read below the",
@@ -706,7 +724,7 @@ def tiled_summary(trace_dir: str, fetch_dir: str, write_dir: str, sq1_dir: str, 
              "MFMA%: SQ_VALU_MFMA_BUSY_CYCLES / (1024 SIMDs x GRBM_GUI_ACTIVE/8).  Per-wave counts: per launch.", "",
              f"{'workload':12s} {'kernel':18s} {'n':>3s} {'avg us':>8s} {'read MB':>8s} {'write MB':>8s} {'MFMA%':>6s} "
              f"{'VALU/wave':>9s} {'LDS/wave':>8s} {'LDScf%':>6s} {'wait%':>6s}"]
-    order = {n: i for i, n in enumerate([NAMES[f] for f in FIDS] + ["hybrid", "composition", "copy probe"])}
+    order = {n: i for i, n in enumerate([NAMES[f] for f in FIDS] + PROFILE_PHASES[1:])}
     for (wl, k) in sorted(med, key=lambda t: (order.get(t[0], 99), t[1])):
         v = med[(wl, k)]
         n = len(groups[(wl, k)].get("us", []))
