@@ -192,35 +192,52 @@ __device__ __forceinline__ void flush(Acc<float> &a, float *slot, int q) {
   a.init();
 }
 
-// Pair terms of one pairwise segment for one row, from z written back over the row's x (the
-// slot of each position's variable); lanes over the segment's positions.
+// Pair terms of one pairwise segment for the wave's rows (kRows / kWaves of them, rows wave +
+// kWaves i), from z written back over the rows' x at the slot of each position's variable; lanes
+// take the segment's positions.  A position's successor and variable are read once for all the
+// wave's rows, and those of the next 64 positions are requested before the current ones' terms.
+constexpr int kPairRows = kRows / kWaves;
+static_assert(kPairRows * kWaves == kRows, "pair terms: whole rows per wave");
 template <int K>
-__device__ __forceinline__ void pair_row(const TiledProb &tp, const TiledSeg &sg, const unsigned char *zr,
-                                         const uint16_t *s_goff, float prm, int lane, Acc<float> &a) {
-  const float *coefp = static_cast<const float *>(tp.coef);
+__device__ __forceinline__ void pair_rows(const TiledProb &tp, const TiledSeg &sg, const float *s_rows, int S,
+                                          const uint16_t *s_goff, float prm, int lane, int wave,
+                                          Acc<float> (&m)[kPairRows]) {
+  auto clampp = [&](int pp) { return pp < sg.p1 ? pp : sg.p1 - 1; };
+  int sp = tp.succ[clampp(sg.p0 + lane)];
+  int gi = tp.gidx[clampp(sg.p0 + lane)];
   for (int p0 = sg.p0; p0 < sg.p1; p0 += 64) {
     const int pp = p0 + lane;
-    const int pc = pp < sg.p1 ? pp : sg.p1 - 1;
-    const int sp = tp.succ[pc];
-    const int gi = tp.gidx[pc];
-    const float z = *reinterpret_cast<const float *>(zr + s_goff[pc]);
-    const float zn = *reinterpret_cast<const float *>(zr + s_goff[sp >= 0 ? sp : pc]);
-    const float cf = coefp[pc];
-    if (pp < sg.p1 && gi >= 0 && sp >= 0) {
-      float v[3] = {0.0f, 0.0f, 0.0f};
-      phi<K, float>(v, a.p, z, zn, cf, prm);
-      a.add(0, v[0]);
+    const int pc = clampp(pp);
+    const bool live = pp < sg.p1 && gi >= 0 && sp >= 0;
+    const uint32_t go = s_goff[pc];
+    const uint32_t gn = s_goff[sp >= 0 ? sp : pc];
+    const int pn = clampp(p0 + 64 + lane);
+    const int sp2 = tp.succ[pn];
+    const int gi2 = tp.gidx[pn];
+#pragma unroll
+    for (int i = 0; i < kPairRows; ++i) {
+      const unsigned char *zr = reinterpret_cast<const unsigned char *>(s_rows + (wave + kWaves * i) * S);
+      const float z = *reinterpret_cast<const float *>(zr + go);
+      const float zn = *reinterpret_cast<const float *>(zr + gn);
+      if (live) {
+        float v[3] = {0.0f, 0.0f, 0.0f};
+        phi<K, float>(v, m[i].p, z, zn, 0.0f, prm);
+        m[i].add(0, v[0]);
+      }
     }
+    sp = sp2;
+    gi = gi2;
   }
 }
 
-__device__ __forceinline__ void pair_row_any(const TiledProb &tp, const TiledSeg &sg, const unsigned char *zr,
-                                             const uint16_t *s_goff, float prm, int lane, Acc<float> &a) {
+__device__ __forceinline__ void pair_rows_any(const TiledProb &tp, const TiledSeg &sg, const float *s_rows, int S,
+                                              const uint16_t *s_goff, float prm, int lane, int wave,
+                                              Acc<float> (&m)[kPairRows]) {
   switch (sg.kind) {
-    case K_F7: pair_row<K_F7>(tp, sg, zr, s_goff, prm, lane, a); break;
-    case K_GRIEROSEN: pair_row<K_GRIEROSEN>(tp, sg, zr, s_goff, prm, lane, a); break;
-    case K_ROSENBROCK: pair_row<K_ROSENBROCK>(tp, sg, zr, s_goff, prm, lane, a); break;
-    case K_F6: pair_row<K_F6>(tp, sg, zr, s_goff, prm, lane, a); break;
+    case K_F7: pair_rows<K_F7>(tp, sg, s_rows, S, s_goff, prm, lane, wave, m); break;
+    case K_GRIEROSEN: pair_rows<K_GRIEROSEN>(tp, sg, s_rows, S, s_goff, prm, lane, wave, m); break;
+    case K_ROSENBROCK: pair_rows<K_ROSENBROCK>(tp, sg, s_rows, S, s_goff, prm, lane, wave, m); break;
+    case K_F6: pair_rows<K_F6>(tp, sg, s_rows, S, s_goff, prm, lane, wave, m); break;
     default: break;
   }
 }
@@ -256,16 +273,35 @@ __device__ __forceinline__ void load_row(__amdgpu_buffer_rsrc_t rs, int D, float
 
 constexpr int kWaitVmem = 0x3F70;  // s_waitcnt vmcnt(0), other counters free (gfx9 encoding)
 
-// Stages rows [row0, row0 + 32) of x (past n: zeros) at stride S, then barrier.  The zero slot
-// (column D) of every row is rewritten too: padded positions gather it.
-__device__ __forceinline__ void stage_rows(const float *x, int row0, int n, int D, int S, float *s_rows, bool wide,
+// Issues the loads that bring rows [row0, row0 + 32) of x (past n: zeros) into LDS at stride S.
+__device__ __forceinline__ void issue_rows(const float *x, int row0, int n, int D, int S, float *s_rows, bool wide,
                                            int lane, int wave) {
   const __amdgpu_buffer_rsrc_t rs = rows_rsrc(x, row0, n, D);
   for (int rr = wave; rr < kRows; rr += kWaves) load_row(rs, D, s_rows + rr * S, rr * 4 * D, wide, lane);
+}
+
+// Waits for the rows issue_rows requested, rewrites the zero slot (column D) of every row, which
+// padded positions gather, then barrier.
+__device__ __forceinline__ void finish_rows(int D, int S, float *s_rows) {
   if (threadIdx.x < kRows) s_rows[threadIdx.x * S + D] = 0.0f;
   __builtin_amdgcn_s_waitcnt(kWaitVmem);
   __syncthreads();
 }
+
+__device__ __forceinline__ void stage_rows(const float *x, int row0, int n, int D, int S, float *s_rows, bool wide,
+                                           int lane, int wave) {
+  issue_rows(x, row0, n, D, S, s_rows, wide, lane, wave);
+  finish_rows(D, S, s_rows);
+}
+
+// The rows of the workgroup's next tile, requested as soon as the last rotation step of the
+// current tile has read its rows (row0 < 0: none, or the problem has pair terms, whose z stays
+// in the rows until the end of the tile).
+struct NextRows {
+  const float *x;
+  int row0, n, D;
+  bool wide;
+};
 
 // One problem (basic function or hybrid) on the rows staged in LDS: every rotation block, the
 // formula terms and row sums, the pair terms.  Returns, in wave 0 lanes < 32, the sum of the
@@ -278,7 +314,7 @@ __device__ __forceinline__ void stage_rows(const float *x, int row0, int n, int 
 template <int NT, int KIND, int AHEAD>
 __device__ __forceinline__ float eval_tile(const TiledProb &tp, float *s_rows, int S, const uint16_t *s_goff,
                                            const float *s_ohp, unsigned char *s_ring, float *s_red, int lane,
-                                           int wave) {
+                                           int wave, const NextRows &nx) {
   const int r = lane & 15, q = lane >> 4;
   const float *czp = static_cast<const float *>(tp.cz);
   const float *cfp = static_cast<const float *>(tp.coef);
@@ -351,6 +387,15 @@ __device__ __forceinline__ float eval_tile(const TiledProb &tp, float *s_rows, i
       for (int j = 0; j < kMW; ++j) {
         act[j] = mbase + kWaves * j < mts;
         mt[j] = act[j] ? mbase + kWaves * j : mts - 1;
+      }
+      // the epilogue's per-position tables, read now: no global load follows the next tile's
+      // row requests, whose completion a later load would otherwise wait for
+      f32x4 cz4[kMW], cf4[kMW];
+#pragma unroll
+      for (int j = 0; j < kMW; ++j) {
+        const int pm = blk.x + 16 * mt[j] + 4 * q;  // 4 consecutive packed positions
+        cz4[j] = *reinterpret_cast<const f32x4 *>(czp + pm);
+        cf4[j] = *reinterpret_cast<const f32x4 *>(cfp + pm);
       }
       // rotation tiles through buffer loads: per-lane offset fixed, tile offset scalar
       auto load_a = [&](bf16x8 (&au)[kMW][NT], int c) {
@@ -426,29 +471,30 @@ __device__ __forceinline__ float eval_tile(const TiledProb &tp, float *s_rows, i
 #pragma unroll
       for (int k = 0; k < kAhead - 1; ++k)
         if (c + k < nst) step(c + k, ar[k]);
+      // every read of the rows is done (the last step ended with a barrier)
+      if (nx.row0 >= 0 && b == tp.nblocks - 1 && pass == npass - 1)
+        issue_rows(nx.x, nx.row0, nx.n, nx.D, S, s_rows, nx.wide, lane, wave);
       // epilogue: z = acc + c' per position; terms into the wave's row sums, or z over the x of
       // the position's variable for pair terms (padding: z = 0 into the zero slot, unchanged)
 #pragma unroll
       for (int j = 0; j < kMW; ++j) {
         if (!act[j]) continue;
         const int pm = blk.x + 16 * (mbase + kWaves * j) + 4 * q;  // 4 consecutive packed positions
-        const f32x4 cz4 = *reinterpret_cast<const f32x4 *>(czp + pm);
         if (pairseg) {
           const uint2 g2 = *reinterpret_cast<const uint2 *>(s_goff + pm);
           const uint32_t go[4] = {g2.x & 0xFFFFu, g2.x >> 16, g2.y & 0xFFFFu, g2.y >> 16};
 #pragma unroll
           for (int cb = 0; cb < kCB; ++cb) {
             unsigned char *row = reinterpret_cast<unsigned char *>(s_rows + (16 * cb + r) * S);
-            const f32x4 z = acc[j][cb] + cz4;
+            const f32x4 z = acc[j][cb] + cz4[j];
 #pragma unroll
             for (int e = 0; e < 4; ++e) *reinterpret_cast<float *>(row + go[e]) = z[e];
           }
         } else {
-          const f32x4 cf4 = *reinterpret_cast<const f32x4 *>(cfp + pm);
 #pragma unroll
           for (int cb = 0; cb < kCB; ++cb) {
-            if constexpr (KIND >= 0) terms<(KIND >= 0 ? KIND : 0)>(acc[j][cb], cz4, cf4, prm, a[cb]);
-            else terms_any(kind, acc[j][cb], cz4, cf4, prm, a[cb]);
+            if constexpr (KIND >= 0) terms<(KIND >= 0 ? KIND : 0)>(acc[j][cb], cz4[j], cf4[j], prm, a[cb]);
+            else terms_any(kind, acc[j][cb], cz4[j], cf4[j], prm, a[cb]);
           }
         }
       }
@@ -464,24 +510,31 @@ __device__ __forceinline__ float eval_tile(const TiledProb &tp, float *s_rows, i
   if (any_pairs) {
     // pair terms: each wave takes rows, lanes the positions of each pairwise segment; the row's
     // pair value goes to slot 0 of its partials (no other use now)
-    for (int rr = wave; rr < kRows; rr += kWaves) {
-      float fr = 0.0f;
-      for (int si = 0; si < tp.nsegs; ++si) {
-        const TiledSeg &ps = tp.segs[si];
-        if (!ps.pairwise) continue;
-        Acc<float> m;
-        m.init();
-        pair_row_any(tp, ps, reinterpret_cast<const unsigned char *>(s_rows + rr * S), s_goff, seg_param(ps), lane, m);
+    float fr[kPairRows];
+#pragma unroll
+    for (int i = 0; i < kPairRows; ++i) fr[i] = 0.0f;
+    for (int si = 0; si < tp.nsegs; ++si) {
+      const TiledSeg &ps = tp.segs[si];
+      if (!ps.pairwise) continue;
+      Acc<float> m[kPairRows];
+#pragma unroll
+      for (int i = 0; i < kPairRows; ++i) m[i].init();
+      pair_rows_any(tp, ps, s_rows, S, s_goff, seg_param(ps), lane, wave, m);
+#pragma unroll
+      for (int i = 0; i < kPairRows; ++i) {
 #pragma unroll
         for (int sh = 1; sh < 64; sh <<= 1) {
-          const float so = __shfl_xor(m.s[0], sh, 64);
-          const float co = __shfl_xor(m.c[0], sh, 64);
-          acc_merge(m, 0, so, co);
+          const float so = __shfl_xor(m[i].s[0], sh, 64);
+          const float co = __shfl_xor(m[i].c[0], sh, 64);
+          acc_merge(m[i], 0, so, co);
         }
-        float sm[3] = {m.get_minus(0, ps.padc[0]), 0.0f, 0.0f};
-        fr += finalize_kind<float>(ps.kind, sm, 1.0f, ps.n);
+        float sm[3] = {m[i].get_minus(0, ps.padc[0]), 0.0f, 0.0f};
+        fr[i] += finalize_kind<float>(ps.kind, sm, 1.0f, ps.n);
       }
-      if (lane == 0) s_red[rr * kSlots] = fr;
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int i = 0; i < kPairRows; ++i) s_red[(wave + kWaves * i) * kSlots] = fr[i];
     }
     __syncthreads();
     if (wave == 0 && lane < kRows) F += s_red[lane * kSlots];
@@ -514,11 +567,17 @@ __global__ __launch_bounds__(kThreads) void k_rowres(TiledProb tp, const float *
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int ntiles = (n + kRows - 1) / kRows;
   load_tables(tp, s_goff, s_ohp);
+  // the next tile's rows are requested inside eval_tile (problems without pair terms)
+  bool requested = false;
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int row0 = tile * kRows;
     __syncthreads();  // the previous tile's readers of the rows are done
-    stage_rows(x, row0, n, D, S, s_rows, wide != 0, lane, wave);
-    const float F = eval_tile<NT, KIND, NT == 2 ? 4 : 3>(tp, s_rows, S, s_goff, s_ohp, s_ring, s_red, lane, wave);
+    if (!requested) issue_rows(x, row0, n, D, S, s_rows, wide != 0, lane, wave);
+    finish_rows(D, S, s_rows);
+    const int next = tile + static_cast<int>(gridDim.x);
+    const NextRows nx{x, next < ntiles && !tp.any_pairwise ? next * kRows : -1, n, D, wide != 0};
+    const float F = eval_tile<NT, KIND, NT == 2 ? 4 : 3>(tp, s_rows, S, s_goff, s_ohp, s_ring, s_red, lane, wave, nx);
+    requested = nx.row0 >= 0;
     if (wave == 0 && lane < kRows && row0 + lane < n) out[row0 + lane] = F + static_cast<float>(tp.bias);
   }
 }
@@ -658,8 +717,9 @@ __global__ __launch_bounds__(kThreads) void k_rowres_comp(const CompDesc *__rest
         __syncthreads();  // the previous component's readers of the tables are done
         load_tables(cd.tp, s_goff, s_ohp);
         __syncthreads();
-        if (cd.six) G = eval_tile<3, -1, 2>(cd.tp, s_rows, S, s_goff, s_ohp, s_ring, s_red, lane, wave);
-        else G = eval_tile<2, -1, 3>(cd.tp, s_rows, S, s_goff, s_ohp, s_ring, s_red, lane, wave);
+        const NextRows none{x, -1, n, D, false};
+        if (cd.six) G = eval_tile<3, -1, 2>(cd.tp, s_rows, S, s_goff, s_ohp, s_ring, s_red, lane, wave, none);
+        else G = eval_tile<2, -1, 3>(cd.tp, s_rows, S, s_goff, s_ohp, s_ring, s_red, lane, wave, none);
       }
       if (wave == 0 && lane < kRows) s_g[cd.index * kRows + lane] = G;
     }
