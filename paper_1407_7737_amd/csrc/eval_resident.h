@@ -309,15 +309,22 @@ __device__ __forceinline__ void gather_b(typename RotOps<P>::Frag (&bf)[RotOps<P
         const f32x4 oa = *reinterpret_cast<const f32x4 *>(s_ohp + kt * 32 + q * 8);
         const f32x4 ob = *reinterpret_cast<const f32x4 *>(s_ohp + kt * 32 + q * 8 + 4);
         const float ov[8] = {oa[0], oa[1], oa[2], oa[3], ob[0], ob[1], ob[2], ob[3]};
+        // the k-tile's eight element reads are issued together, then the cuts
+        float xv[NB][8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const uint32_t oe = (e & 1) ? iw[e >> 1] >> 16 : iw[e >> 1] & 0xFFFFu;
+#pragma unroll
+          for (int b = 0; b < NB; ++b) xv[b][e] = *reinterpret_cast<const float *>(Yb + b * bstride + oe);
+        }
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int e = 0; e < 8; e += 2) {
           // two elements at a time: one packed conversion per term for the pair
-          const uint32_t o0 = iw[e >> 1] & 0xFFFFu, o1 = iw[e >> 1] >> 16;
           const f32x2 oo = {ov[e], ov[e + 1]};
 #pragma unroll
           for (int b = 0; b < NB; ++b) {
-            const f32x2 y = f32x2{*reinterpret_cast<const float *>(Yb + b * bstride + o0),
-                                  *reinterpret_cast<const float *>(Yb + b * bstride + o1)} - oo;
+            const f32x2 y = f32x2{xv[b][e], xv[b][e + 1]} - oo;
             cut_terms<P>(bf, b, kt, e, y);
           }
         }
@@ -344,12 +351,17 @@ __device__ __forceinline__ void gather_pre(typename RotOps<P>::Frag (&bf)[RotOps
     if (kt < KT) {
       const f32x4 oa = *reinterpret_cast<const f32x4 *>(s_ohp + kt * 32 + q * 8);
       const f32x4 ob = *reinterpret_cast<const f32x4 *>(s_ohp + kt * 32 + q * 8 + 4);
+      // the k-tile's eight element reads are issued together, then the cuts (left to itself the
+      // compiler waits for each pair of reads before its cut)
+      float xv[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) xv[e] = *reinterpret_cast<const float *>(lds + ga[kt * 8 + e]);
+      __builtin_amdgcn_sched_barrier(0);
       const float ov[8] = {oa[0], oa[1], oa[2], oa[3], ob[0], ob[1], ob[2], ob[3]};
 #pragma unroll
       for (int e = 0; e < 8; e += 2) {
         const f32x2 oo = {ov[e], ov[e + 1]};
-        const f32x2 y = f32x2{*reinterpret_cast<const float *>(lds + ga[kt * 8 + e]),
-                              *reinterpret_cast<const float *>(lds + ga[kt * 8 + e + 1])} - oo;
+        const f32x2 y = f32x2{xv[e], xv[e + 1]} - oo;
         cut_terms<P>(bf, 0, kt, e, y);
       }
     }
@@ -387,8 +399,10 @@ __device__ __forceinline__ void mtile(typename PathT<P>::Acc4 (&acc)[blocks_of(P
 }
 
 // One m-tile on the split paths for a k range fixed at compile time (k-tiles KX .. KX+NK-1):
-// the range's rotation fragments are read from LDS together, ahead of the first product, so
-// one LDS latency is exposed per m-tile, and the products run with no branch between them.
+// each k-tile's rotation fragments are requested from LDS before the previous k-tile's products
+// are issued (held apart by a scheduling barrier; left to itself the compiler reuses one register
+// set and waits for every read next to its product), and the products run with no branch
+// between them.
 template <int P, int KX, int NK>
 __device__ __forceinline__ void mtile_fixed(typename PathT<P>::Acc4 (&acc)[blocks_of(P)], int t0,
                                             const bf16x8 (&bf)[RotOps<P>::NTERM][blocks_of(P)][RotOps<P>::KTMAX],
@@ -398,14 +412,17 @@ __device__ __forceinline__ void mtile_fixed(typename PathT<P>::Acc4 (&acc)[block
   const bf16x8 *qf = reinterpret_cast<const bf16x8 *>(s_q) + t0 * (64 * NT) + lane;
   bf16x8 qa[NK][NT];
 #pragma unroll
-  for (int j = 0; j < NK; ++j)
-#pragma unroll
-    for (int u = 0; u < NT; ++u) qa[j][u] = qf[(j * NT + u) * 64];
+  for (int u = 0; u < NT; ++u) qa[0][u] = qf[u * 64];
 #pragma unroll
   for (int b = 0; b < NB; ++b) acc[b] = f32x4{0, 0, 0, 0};
 #pragma unroll
   for (int j = 0; j < NK; ++j) {
     const int kt = KX + j;
+    if (j + 1 < NK) {
+#pragma unroll
+      for (int u = 0; u < NT; ++u) qa[j + 1][u] = qf[((j + 1) * NT + u) * 64];
+    }
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       if constexpr (NT == 3) {
