@@ -311,7 +311,8 @@ struct NextRows {
 // KIND >= 0: one formula family (basic functions); KIND < 0: family per segment at run time
 // (hybrids, composition components).  NT: bf16 terms per operand (2: three products, 3: six).
 // AHEAD: steps the rotation tiles are requested ahead of their products (registers permitting).
-template <int NT, int KIND, int AHEAD>
+// LEAN (the fused composition kernel, short of registers): the epilogue reads its tables itself.
+template <int NT, int KIND, int AHEAD, bool LEAN = false>
 __device__ __forceinline__ float eval_tile(const TiledProb &tp, float *s_rows, int S, const uint16_t *s_goff,
                                            const float *s_ohp, unsigned char *s_ring, float *s_red, int lane,
                                            int wave, const NextRows &nx) {
@@ -391,12 +392,15 @@ __device__ __forceinline__ float eval_tile(const TiledProb &tp, float *s_rows, i
       // the epilogue's per-position tables, read now: no global load follows the next tile's
       // row requests, whose completion a later load would otherwise wait for
       f32x4 cz4[kMW], cf4[kMW];
+      auto read_epi = [&]() {
 #pragma unroll
-      for (int j = 0; j < kMW; ++j) {
-        const int pm = blk.x + 16 * mt[j] + 4 * q;  // 4 consecutive packed positions
-        cz4[j] = *reinterpret_cast<const f32x4 *>(czp + pm);
-        cf4[j] = *reinterpret_cast<const f32x4 *>(cfp + pm);
-      }
+        for (int j = 0; j < kMW; ++j) {
+          const int pm = blk.x + 16 * mt[j] + 4 * q;  // 4 consecutive packed positions
+          cz4[j] = *reinterpret_cast<const f32x4 *>(czp + pm);
+          cf4[j] = *reinterpret_cast<const f32x4 *>(cfp + pm);
+        }
+      };
+      if constexpr (!LEAN) read_epi();
       // rotation tiles through buffer loads: per-lane offset fixed, tile offset scalar
       auto load_a = [&](bf16x8 (&au)[kMW][NT], int c) {
 #pragma unroll
@@ -476,6 +480,7 @@ __device__ __forceinline__ float eval_tile(const TiledProb &tp, float *s_rows, i
         issue_rows(nx.x, nx.row0, nx.n, nx.D, S, s_rows, nx.wide, lane, wave);
       // epilogue: z = acc + c' per position; terms into the wave's row sums, or z over the x of
       // the position's variable for pair terms (padding: z = 0 into the zero slot, unchanged)
+      if constexpr (LEAN) read_epi();
 #pragma unroll
       for (int j = 0; j < kMW; ++j) {
         if (!act[j]) continue;
@@ -718,8 +723,8 @@ __global__ __launch_bounds__(kThreads) void k_rowres_comp(const CompDesc *__rest
         load_tables(cd.tp, s_goff, s_ohp);
         __syncthreads();
         const NextRows none{x, -1, n, D, false};
-        if (cd.six) G = eval_tile<3, -1, 2>(cd.tp, s_rows, S, s_goff, s_ohp, s_ring, s_red, lane, wave, none);
-        else G = eval_tile<2, -1, 3>(cd.tp, s_rows, S, s_goff, s_ohp, s_ring, s_red, lane, wave, none);
+        if (cd.six) G = eval_tile<3, -1, 2, true>(cd.tp, s_rows, S, s_goff, s_ohp, s_ring, s_red, lane, wave, none);
+        else G = eval_tile<2, -1, 3, true>(cd.tp, s_rows, S, s_goff, s_ohp, s_ring, s_red, lane, wave, none);
       }
       if (wave == 0 && lane < kRows) s_g[cd.index * kRows + lane] = G;
     }
