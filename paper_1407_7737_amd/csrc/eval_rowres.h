@@ -9,16 +9,19 @@
 //     32 packed positions for the 32 rows, cut into bf16 terms) is produced once per workgroup,
 //     one pair of positions of one row per thread, into a two-slot LDS ring in MFMA operand
 //     order, one barrier per step; every wave then reads it with one 16-byte LDS read per
-//     (column block, term).  The rotation tiles (A operand) stream from L2, two steps ahead;
+//     (column block, term).  The rotation tiles (A operand) stream from L2 through buffer loads
+//     issued several steps ahead of their products (four for three products, three for six);
 //   - z = acc + c' then the formula's per-element terms go into the wave's compensated row
 //     sums.  Formulas with pair terms instead write z back into the LDS rows, at the slot of
 //     the position's own variable (the block's variables are read by no later step), and the
 //     pair terms are summed from there once every block is done;
 //   - row sums of all waves meet in LDS, in wave order, and wave 0 finalises each formula
 //     segment of its rows.
-// The rows reach LDS through buffer loads that write LDS directly.  X is read from HBM once,
-// nothing goes through scratch memory, and the result row is written directly.  Persistent
-// grid: each workgroup walks row tiles with a stride of the grid.
+// The rows reach LDS through buffer loads that write LDS directly; for problems without pair
+// terms the next tile's rows are requested as soon as the current tile's last rotation step has
+// read its rows.  X is read from HBM once, nothing goes through scratch memory, and the result
+// row is written directly.  Persistent grid: each workgroup walks row tiles with a stride of the
+// grid.
 #pragma once
 
 #include <hip/hip_runtime.h>
