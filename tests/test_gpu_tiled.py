@@ -475,3 +475,25 @@ def test_beyond_row_resident_dimension(env):
         allow = basic_allowance(orc, fid, p.shift(), p.rotation(), x32w)
         for m in f:
             say(f"[d1100] fid={fid} mode={m} max {check32(f[m], ref32, allow, (m, fid)):.3e}")
+
+
+def test_row_resident_many_tiles_per_workgroup(env):
+    """The row-resident kernel walking several 32-row tiles per workgroup (a persistent grid of
+    one workgroup per CU over 24,589 rows at D = 300, the last tile ragged): every row against
+    the oracle.  Without pair terms the next tile's rows are requested while the current tile
+    finishes; Rosenbrock (pair terms) keeps its z in the rows and requests them after."""
+    c, orc, torch, use = env
+    n = 32 * 256 * 3 + 13
+    use(300, maxc=n)
+    from paper_1407_7737_amd.inputs import population, near
+    for fid in (2, 11, 14, 16, 19):
+        say(f"[rowres-tiles] fid={fid} n={n}")
+        p = orc.basic(fid, 300, SEED)
+        x = population(n, 300, seed=100 + fid)
+        x[-200:] = near(np.repeat(p.shift()[None, :], 200, axis=0), 0.5, seed=fid)
+        x32 = x.astype(np.float32)
+        f = c.func_evaluatef(fid, torch.from_numpy(x32).cuda()).cpu().numpy().astype(np.float64)
+        x32w = x32.astype(np.float64)
+        ref32 = p(x32w, threads=16)
+        allow = basic_allowance(orc, fid, p.shift(), p.rotation(), x32w)
+        check32(f, ref32, allow, ("rowres-tiles", fid))
