@@ -477,6 +477,27 @@ def test_beyond_row_resident_dimension(env):
             say(f"[d1100] fid={fid} mode={m} max {check32(f[m], ref32, allow, (m, fid)):.3e}")
 
 
+@pytest.mark.parametrize("dim", [1056, 1088])
+def test_row_resident_largest_dimensions(env, dim):
+    """The row-resident kernel's LDS limit: at D = 1088 the three-product carve (32 rows plus
+    tables, ring and row sums) still fits 160 KB and the six-product one does not (the tiled
+    kernels take it); at D = 1056 both fit.  A formula of each kind and one with pair terms (24
+    m-tiles per block, the most one pass covers), every mode, against the oracle."""
+    c, orc, torch, use = env
+    use(dim)
+    from paper_1407_7737_amd.inputs import population
+    x = population(80, dim, seed=dim)
+    for fid in (11, 14, 16):
+        say(f"[rowres-limit] dim={dim} fid={fid}")
+        p = orc.basic(fid, dim, SEED)
+        x32w, f64, f = run_paths(c, torch, fid, x, all_modes(c))
+        assert rel_err(f64, p(x, threads=16)).max() <= TOL64
+        ref32 = p(x32w, threads=16)
+        allow = basic_allowance(orc, fid, p.shift(), p.rotation(), x32w)
+        for m in f:
+            check32(f[m], ref32, allow, (m, dim, fid))
+
+
 def test_row_resident_many_tiles_per_workgroup(env):
     """The row-resident kernel walking several 32-row tiles per workgroup (a persistent grid of
     one workgroup per CU over 24,589 rows at D = 300, the last tile ragged): every row against
