@@ -70,9 +70,14 @@ enum curob_fid {
 /* Performs all set-up (Sec. 1.3 "Interface"): draws every function's optimum o uniformly in
  * [-70,70]^dim and its rotation from three random, almost equal variable groups, each block
  * an orthonormalised matrix of N(0,1) entries (Sec. 1.2), all from `seed`; uploads them to the
- * current HIP device and reserves staging for max_concurrency rows.  dim >= 2 (Sec. 1.2);
- * hybrid ids need dim >= 10.  Errors: CUROB_E_STATE if already initialised, CUROB_E_ARG for
- * dim < 2 or max_concurrency < 1, CUROB_E_HIP if no device or memory is available. */
+ * current HIP device and reserves staging for max_concurrency rows.  dim >= 2 (Sec. 1.2).
+ * A Tab. 1 id whose definition leaves it undefined at this dimension is left out, and every
+ * call for it returns CUROB_E_FID with the reason: the hybrids (and compositions 35 and 36)
+ * below dim 10, and hybrids 27 and 28 (and composition 36, built on them) at dim 11 and 12,
+ * where their last group, the remainder after four rounded-up shares (Sec. 5, Eq. (numbers)),
+ * gets fewer variables than its formula needs.  Errors: CUROB_E_STATE if already initialised,
+ * CUROB_E_ARG for dim < 2 or max_concurrency < 1, CUROB_E_HIP if no device or memory is
+ * available. */
 int initialize(int dim, int max_concurrency, unsigned long long seed);
 
 /* Releases everything initialize and later calls allocated (Sec. 1.3).  Returns CUROB_E_STATE

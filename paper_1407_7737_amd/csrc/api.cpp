@@ -53,6 +53,8 @@ struct Context {
   int mode = CUROB_MODE_SPLIT;
   hipStream_t stream = nullptr;
   std::map<int, std::unique_ptr<Entry>> entries;
+  // Tab. 1 ids whose definition leaves them undefined at this dimension, with the reason
+  std::map<int, std::string> undefined;
   CompositeScratch scratch;   // tiled partial sums, pairwise z, composition components
   void *stage_x = nullptr;    // maxc * dim doubles, for the h_ wrappers
   void *stage_out = nullptr;  // maxc doubles
@@ -147,6 +149,14 @@ int fp32_path(int fid) {
   return problem_needs_six(p) ? PATH_SPLIT6 : PATH_SPLIT;
 }
 
+// An id without an entry: undefined at this dimension (with the reason), or never registered.
+int not_defined(int fid) {
+  auto u = g_ctx.undefined.find(fid);
+  if (u != g_ctx.undefined.end())
+    return fail(CUROB_E_FID, "function id %d is not defined for dim %d: %s", fid, g_ctx.dim, u->second.c_str());
+  return fail(CUROB_E_FID, "function id %d is not defined for dim %d", fid, g_ctx.dim);
+}
+
 int check_ready() {
   if (!g_ctx.ready) return fail(CUROB_E_STATE, "library is not initialised (call initialize first)");
   return CUROB_OK;
@@ -156,7 +166,7 @@ int check_eval_args(int fid, const void *x, int n, const void *out, Entry **entr
   int rc = check_ready();
   if (rc != CUROB_OK) return rc;
   auto it = g_ctx.entries.find(fid);
-  if (it == g_ctx.entries.end()) return fail(CUROB_E_FID, "function id %d is not defined for dim %d", fid, g_ctx.dim);
+  if (it == g_ctx.entries.end()) return not_defined(fid);
   if (n < 0) return fail(CUROB_E_ARG, "n must be >= 0 (got %d)", n);
   if (n > g_ctx.maxc) return fail(CUROB_E_CAPACITY, "n = %d exceeds max_concurrency %d", n, g_ctx.maxc);
   if (n > 0 && (x == nullptr || out == nullptr)) return fail(CUROB_E_ARG, "null pointer with n > 0");
@@ -275,7 +285,7 @@ int find_entry(int fid, const Problem **p) {
   int rc = check_ready();
   if (rc != CUROB_OK) return rc;
   auto it = g_ctx.entries.find(fid);
-  if (it == g_ctx.entries.end()) return fail(CUROB_E_FID, "function id %d is not defined", fid);
+  if (it == g_ctx.entries.end()) return not_defined(fid);
   *p = &it->second->host;
   return CUROB_OK;
 }
@@ -323,9 +333,18 @@ int initialize(int dim, int max_concurrency, unsigned long long seed) {
   g_ctx.seed = seed;
   try {
     for (int fid = 0; fid <= 36; ++fid) {
-      if (fid >= 23 && fid <= 28 && dim < 10) continue;  // hybrids need dim >= 10 (Sec. 1.2)
-      if ((fid == 35 || fid == 36) && dim < 10) continue;
-      int rc = register_problem(fid, make_tab1(fid, dim, seed));
+      // Sec. 5 defines a hybrid only where each group gets the variables its formula needs:
+      // below 10 variables, and for hybrids 27 and 28 at 11 and 12 (their last group, the
+      // remainder after four rounded-up shares, gets 0 or 1), the id (and any composition built
+      // on it) is left out; a call for it returns the reason
+      Problem p;
+      try {
+        p = make_tab1(fid, dim, seed);
+      } catch (const std::invalid_argument &ex) {
+        g_ctx.undefined[fid] = ex.what();
+        continue;
+      }
+      int rc = register_problem(fid, std::move(p));
       if (rc != CUROB_OK) {
         free_context();
         return rc;
@@ -581,7 +600,7 @@ int curob_get_problem(int fid, double *o, double *R) {
   int rc = check_ready();
   if (rc != CUROB_OK) return rc;
   auto it = g_ctx.entries.find(fid);
-  if (it == g_ctx.entries.end()) return fail(CUROB_E_FID, "function id %d is not defined", fid);
+  if (it == g_ctx.entries.end()) return not_defined(fid);
   const Problem &p = it->second->host;
   if (p.type != Problem::BASIC) return fail(CUROB_E_FID, "id %d is not a basic function", fid);
   if (o) std::memcpy(o, p.o.data(), sizeof(double) * p.dim);

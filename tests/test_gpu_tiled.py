@@ -186,6 +186,28 @@ def test_paper_hybrids(env, dim):
             check32(f[m], ref32, allow, (m, dim, fid))
 
 
+@pytest.mark.parametrize("dim", [11, 12])
+def test_hybrids_undefined_at_small_dimensions(env, dim):
+    """At 11 and 12 variables the last group of hybrids 27 and 28 (the remainder after shares of
+    ceil(0.1 D), then three of ceil(0.2 D)) gets 0 or 1 variables, too few for its formula
+    (Sec. 5, Eq. (numbers)).  initialize succeeds; those ids and composition 36 (built on them)
+    report CUROB_E_FID with the reason; the other hybrids and the basic functions evaluate."""
+    c, orc, torch, use = env
+    use(dim)
+    from paper_1407_7737_amd.inputs import population
+    x = population(40, dim, seed=dim)
+    dx = torch.from_numpy(x).cuda()
+    undefined = {27, 36} | ({28} if dim == 11 else set())
+    for fid in sorted(undefined):
+        with pytest.raises(c.CurobError) as ei:
+            c.func_evaluate(fid, dx)
+        assert ei.value.code == c.CUROB_E_FID and "not defined for dim" in str(ei.value), (fid, str(ei.value))
+    for fid in [0, 11, 23, 24, 25, 26, 35] + ([28] if dim == 12 else []):
+        p = orc.fid_problem(fid, dim, SEED)
+        f = c.func_evaluate(fid, dx).cpu().numpy()
+        assert rel_err(f, p(x)).max() <= TOL64, (dim, fid)
+
+
 # component ids of the paper's compositions (Sec. 6); ids >= 23 are the hybrids of Sec. 5
 COMPOSITION_G = {29: [14, 2, 4, 3, 2], 30: [15, 11, 21], 31: [16, 11, 2], 32: [16, 20, 2, 8, 9],
                  33: [21, 11, 16, 8, 2], 34: [13, 20, 16, 22, 2], 35: [23, 24, 25], 36: [26, 27, 28]}
