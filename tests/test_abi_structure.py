@@ -136,3 +136,28 @@ def test_binding_rejects_wrong_row_width(curob):
             curob.get_problem(0, 11)
     finally:
         curob._dim = old
+
+
+def test_undefined_hybrids_match_the_oracle():
+    """Where the group sizes of Sec. 5 (n_i = ceil(p_i D), the last group the remainder) give a
+    group fewer variables than its formula needs, the hybrid (and a composition built on it) is
+    undefined.  The library's host generator and the oracle's refuse exactly the same (id, D)
+    pairs over D = 2..200: every hybrid below 10, hybrids 27 and 28 and composition 36 at 11,
+    hybrid 27 and composition 36 at 12, nothing else."""
+    import oracle
+    import paper_1407_7737_amd as curob
+    lib = curob.lib
+    kind = ctypes.c_int()
+    refused_lib, refused_orc = set(), set()
+    for dim in range(2, 201):
+        for fid in (23, 24, 25, 26, 27, 28, 35, 36):
+            if lib.curob_generate_info(fid, dim, 0, -1, ctypes.byref(kind), None, None) != curob.CUROB_OK:
+                refused_lib.add((fid, dim))
+            try:
+                oracle.fid_problem(fid, dim, 0)
+            except ValueError:
+                refused_orc.add((fid, dim))
+    expected = {(f, d) for f in (23, 24, 25, 26, 27, 28, 35, 36) for d in range(2, 10)}
+    expected |= {(27, 11), (28, 11), (36, 11), (27, 12), (36, 12)}
+    assert refused_lib == expected, sorted(refused_lib ^ expected)
+    assert refused_orc == expected, sorted(refused_orc ^ expected)
