@@ -540,3 +540,30 @@ def test_row_resident_many_tiles_per_workgroup(env):
         ref32 = p(x32w, threads=16)
         allow = basic_allowance(orc, fid, p.shift(), p.rotation(), x32w)
         check32(f, ref32, allow, ("rowres-tiles", fid))
+
+
+LARGE_DIMS = [129, 131, 160, 161, 192, 193, 257, 333, 512, 513, 769, 999, 1025, 1060, 1089, 1200]
+
+
+def test_large_dimension_sweep(env):
+    """Dimensions above the resident range around the paddings (blocks padded to 32 positions, 16
+    outputs per m-tile, 24 m-tiles per row-resident pass) and the row-resident kernel's LDS limit:
+    an unrotated, a rotated, a pair-term and a six-product formula and two hybrids (one with a
+    pair-term group), default split mode and FP64, 100 rows each, against the oracle."""
+    c, orc, torch, use = env
+    from paper_1407_7737_amd.inputs import population
+    n = 100
+    for dim in LARGE_DIMS:
+        use(dim, maxc=n)
+        x = population(n, dim, seed=dim)
+        for fid in (0, 11, 14, 16, 25, 27):
+            say(f"[large-dim] dim={dim} fid={fid}")
+            p = orc.fid_problem(fid, dim, SEED)
+            x32w, f64, f = run_paths(c, torch, fid, x, [c.MODE_SPLIT])
+            assert rel_err(f64, p(x, threads=16)).max() <= TOL64, (dim, fid)
+            ref32 = p(x32w, threads=16)
+            if fid >= 23:
+                allow = hybrid_allowance(orc, p, HYBRID_BASES[fid], x32w)
+            else:
+                allow = basic_allowance(orc, fid, p.shift(), p.rotation(), x32w)
+            check32(f[c.MODE_SPLIT], ref32, allow, ("large-dim", dim, fid))
