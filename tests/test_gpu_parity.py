@@ -135,8 +135,8 @@ def test_every_resident_dimension(env):
     """Every dimension the resident kernel takes (2..128): row stride, k- and m-tile counts,
     aligned and unaligned rows, rows loaded straight into LDS or staged through registers.  An
     unrotated formula, a rotated one, one with pair terms and a six-product one, 1000 rows (62
-    row groups and a ragged 8; the Schwefel check bounds the share of rows at a jump), default
-    split mode and FP64, against the oracle."""
+    row groups and a ragged 8; the Schwefel check bounds the share of rows at a jump), every FP32
+    mode and FP64, against the oracle."""
     c, orc, torch, use = env
     from paper_1407_7737_amd.inputs import population
     n = 1000
@@ -146,9 +146,12 @@ def test_every_resident_dimension(env):
             say(f"[every-dim] dim={dim} fid={fid}")
             p = orc.basic(fid, dim, SEED)
             x = population(n, dim, seed=dim)
-            x32w, f64, f = run_paths(c, torch, fid, x, [c.MODE_SPLIT])
+            modes = [c.MODE_SPLIT, c.MODE_FP32, c.MODE_SPLIT_BF16X6] + ([] if six(fid, dim) else [c.MODE_SPLIT_BF16X3])
+            x32w, f64, f = run_paths(c, torch, fid, x, modes)
             assert rel_err(f64, p(x)).max() <= TOL64, (dim, fid)
-            check32(orc, fid, p, x32w, f[c.MODE_SPLIT], p(x32w), ("every-dim", dim))
+            ref32 = p(x32w)
+            for m in modes:
+                check32(orc, fid, p, x32w, f[m], ref32, ("every-dim", dim, m))
 
 
 @pytest.mark.parametrize("n", [1, 2, 15, 16, 17, 63, 64, 65, 257, 4097])
