@@ -567,3 +567,25 @@ def test_large_dimension_sweep(env):
             else:
                 allow = basic_allowance(orc, fid, p.shift(), p.rotation(), x32w)
             check32(f[c.MODE_SPLIT], ref32, allow, ("large-dim", dim, fid))
+
+
+@pytest.mark.parametrize("seed", [1, 2, 12345])
+def test_problem_seed_sweep(env, seed):
+    """Other problem instances (shift, permutation and rotations from other seeds) for the
+    benchmark formulas at D = 10, 100 and 1000: default split mode and FP64 against the oracle,
+    with rows near the optimum included."""
+    c, orc, torch, use = env
+    from paper_1407_7737_amd.inputs import population, near
+    n = 400
+    for dim in (10, 100, 1000):
+        use(dim, maxc=n, seed=seed)
+        for fid in (0, 2, 9, 10, 11, 14, 16, 19):
+            say(f"[seed-sweep] seed={seed} dim={dim} fid={fid}")
+            p = orc.basic(fid, dim, seed)
+            x = population(n, dim, seed=seed + fid)
+            x[:50] = near(np.repeat(p.shift()[None, :], 50, axis=0), 0.5, seed=fid)
+            x32w, f64, f = run_paths(c, torch, fid, x, [c.MODE_SPLIT])
+            assert rel_err(f64, p(x, threads=16)).max() <= TOL64, (seed, dim, fid)
+            ref32 = p(x32w, threads=16)
+            allow = basic_allowance(orc, fid, p.shift(), p.rotation(), x32w)
+            check32(f[c.MODE_SPLIT], ref32, allow, ("seed-sweep", seed, dim, fid))
