@@ -589,3 +589,31 @@ def test_problem_seed_sweep(env, seed):
             ref32 = p(x32w, threads=16)
             allow = basic_allowance(orc, fid, p.shift(), p.rotation(), x32w)
             check32(f[c.MODE_SPLIT], ref32, allow, ("seed-sweep", seed, dim, fid))
+
+
+@pytest.mark.parametrize("seed", [3, 777])
+def test_paper_compositions_other_seeds(env, seed):
+    """The compositions (ids 29-36) and hybrids (23-28) for other problem seeds at D = 30 and
+    100, rows at and near every component optimum included: default split mode and FP64."""
+    c, orc, torch, use = env
+    from paper_1407_7737_amd.inputs import population, near
+    n = 120
+    for dim in (30, 100):
+        use(dim, seed=seed)
+        for fid in range(23, 37):
+            say(f"[seeds] seed={seed} dim={dim} fid={fid}")
+            p = orc.fid_problem(fid, dim, seed)
+            x = population(n, dim, seed=seed + fid)
+            if fid >= 29:
+                gids = COMPOSITION_G[fid]
+                for i in range(len(gids)):
+                    x[i] = p.shift(i)
+                    x[10 + i] = near(p.shift(i)[None, :], 1.0, seed=i)[0]
+            x32w, f64, f = run_paths(c, torch, fid, x, [c.MODE_SPLIT])
+            assert rel_err(f64, p(x, threads=16)).max() <= TOL64, (seed, dim, fid)
+            ref32 = p(x32w, threads=16)
+            if fid >= 29:
+                allow = composition_allowance(orc, p, COMPOSITION_G[fid], x32w)
+            else:
+                allow = hybrid_allowance(orc, p, HYBRID_BASES[fid], x32w)
+            check32(f[c.MODE_SPLIT], ref32, allow, ("seeds", seed, dim, fid))
