@@ -56,7 +56,7 @@ PAPER_CONTEXT = {
                          "schwefel": 14.38, "ackley": 11.32},
     "speedup_d96_fp64": {"griewank": 9.72, "rastrigin_u": 1.78, "rastrigin": 9.62, "rosenbrock": 7.87,
                          "schwefel": 11.91, "ackley": 9.75},
-    "note": "no absolute rates are published; these ratios do not compare with this build's numbers",
+    "note": "no absolute rates are published; these ratios do not compare with this library's numbers",
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_d100_n262144.json")
 KERNEL_SOURCES = ["eval_resident.h", "formulas.h", "devprob.h", "kernels.h"]

@@ -908,7 +908,7 @@ const orc_problem *orc_problem_component(const orc_problem *p, int i) {
 /* ------------------------------------------------------------------------------------------
  * Differential evolution (DE/rand/1/bin) with the FP64 formulas above: the optimiser-in-the-loop
  * use the paper motivates (Sec. 1) and measures with 50 concurrent evaluations (Sec. 2), as a
- * reference for the GPU driver.  Draws are counter based, SplitMix64's output for the state
+ * reference for the GPU optimiser.  Draws are counter based, SplitMix64's output for the state
  * seed + (k + 1) * 0x9E3779B97F4A7C15, draw k = (g * np + i) * (D + 4) + slot for individual i
  * of generation g: slots 0-2 choose r1, r2, r3 among the indices not yet taken (i first), as
  * the v-th remaining index in increasing order with v = draw mod count; slot 3 the forced

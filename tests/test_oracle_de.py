@@ -1,4 +1,4 @@
-"""Pins for the oracle's differential evolution (the reference of the GPU optimiser driver).
+"""Pins for the oracle's differential evolution (the reference of the GPU optimiser).
 
 The oracle's DE is checked against a second implementation of the same specification written
 here in plain Python (exact fused multiply-add through rational arithmetic, SplitMix64 from its
