@@ -653,3 +653,86 @@ def test_custom_basic_sweep(env, dim):
                 z = (y @ p.rotation().T if rotated else y) + offset
                 check32(f, p(x32w, threads=16), edge_jumps(base, z, y), tag)
                 pid += 1
+
+
+def random_cases(count, seed):
+    """Seeded draws of (fid, dim, n, problem seed, max_concurrency, FP32 mode, extra entry
+    point): dimensions over the resident range, the row-resident range and its LDS limit,
+    populations from a single row up, ids the oracle defines at that dimension."""
+    import oracle as orc
+    rng = np.random.default_rng(seed)
+    cases = []
+    while len(cases) < count:
+        u = rng.uniform()
+        dim = int(rng.integers(2, 129)) if u < 0.4 else (int(rng.integers(129, 421)) if u < 0.75
+                                                          else int(rng.integers(421, 1101)))
+        fid = int(rng.integers(0, 37))
+        try:
+            orc.fid_problem(fid, dim, 0)
+        except ValueError:
+            continue
+        top = 5000 if dim <= 128 else (1500 if dim <= 420 else 400)
+        if fid >= 29 and dim > 420:
+            top = 150
+        n = int(np.exp(rng.uniform(0.0, np.log(top))))
+        maxc = max(1, int(n * rng.uniform(1.0, 1.5)))  # calls above max_concurrency rows are refused
+        modes = ["split", "fp32", "x6"] + (["x3"] if fid <= 22 and not six(fid, dim) else [])
+        mode = modes[int(rng.integers(0, len(modes)))]
+        extra = ["none", "host", "noalloc"][int(rng.integers(0, 3))]
+        cases.append((fid, dim, n, int(rng.integers(0, 1 << 31)), maxc, mode, extra))
+    return cases
+
+
+@pytest.mark.parametrize("chunk", [0, 1, 2, 3])
+def test_random_configuration_sweep(env, chunk):
+    """Forty seeded random configurations (ten per chunk): any defined Tab. 1 id, dimensions from
+    2 to 1100, populations from one row up, other problem seeds and max_concurrency, one FP32
+    mode each (default split, FP32-MFMA, six or three products where three meet the bar), rows
+    at and near the optimum (every component optimum for compositions).  FP64 and FP32 against
+    the oracle with the per-row allowances; where drawn, the host entry point must return the
+    device results bit for bit and the allocation-free one must meet the same bar."""
+    c, orc, torch, use = env
+    from paper_1407_7737_amd.inputs import population, near
+    mode_of = {"split": c.MODE_SPLIT, "fp32": c.MODE_FP32, "x6": c.MODE_SPLIT_BF16X6, "x3": c.MODE_SPLIT_BF16X3}
+    for k, (fid, dim, n, pseed, maxc, mode, extra) in enumerate(random_cases(40, 0x7E57)[10 * chunk:10 * chunk + 10]):
+        tag = ("random", 10 * chunk + k, fid, dim, n, pseed, maxc, mode, extra)
+        say(f"[random] case={10 * chunk + k} fid={fid} dim={dim} n={n} seed={pseed} maxc={maxc} mode={mode} extra={extra}")
+        use(dim, maxc=maxc, seed=pseed)
+        p = orc.fid_problem(fid, dim, pseed)
+        x = population(n, dim, seed=pseed % 100003)
+        if fid >= 29:
+            for i in range(min(n, len(COMPOSITION_G[fid]))):
+                x[i] = p.shift(i)
+        else:
+            x[0] = p.shift()
+            m = min(n, 1 + n // 10)
+            if m > 1:
+                x[1:m] = near(np.repeat(p.shift()[None, :], m - 1, axis=0), 0.5, seed=fid)
+        f64 = c.func_evaluate(fid, torch.from_numpy(x).cuda()).cpu().numpy()
+        assert rel_err(f64, p(x, threads=16)).max() <= TOL64, tag
+        x32 = x.astype(np.float32)
+        x32w = x32.astype(np.float64)
+        dx32 = torch.from_numpy(x32).cuda()
+        c.set_mode(mode_of[mode])
+        try:
+            f = c.func_evaluatef(fid, dx32).cpu().numpy()
+            if extra == "host":
+                fh = c.h_func_evaluatef(fid, x32)
+                assert np.array_equal(fh, f), tag
+            elif extra == "noalloc":
+                got = torch.empty(n, dtype=torch.float32, device="cuda")
+                c.check(c.lib.func_evaluatef_noalloc(fid, dx32.data_ptr(), n, got.data_ptr()))
+                fn = got.cpu().numpy()
+            torch.cuda.synchronize()
+        finally:
+            c.set_mode(c.MODE_SPLIT)
+        ref32 = p(x32w, threads=16)
+        if fid >= 29:
+            allow = composition_allowance(orc, p, COMPOSITION_G[fid], x32w)
+        elif fid >= 23:
+            allow = hybrid_allowance(orc, p, HYBRID_BASES[fid], x32w)
+        else:
+            allow = basic_allowance(orc, fid, p.shift(), p.rotation(), x32w)
+        check32(f, ref32, allow, tag)
+        if extra == "noalloc":
+            check32(fn, ref32, allow, tag + ("noalloc",))
