@@ -177,7 +177,8 @@ int curob_get_dim(int *dim, int *max_concurrency);
  * These read the problem registered under fid in the initialised library (CUROB_E_STATE before
  * initialize, CUROB_E_FID for an unknown id).  The curob_generate_* forms generate Tab. 1
  * problem fid (0..36) for (dim, seed) on the host instead, exactly as initialize(dim, ..., seed)
- * would, with no device and no library state (CUROB_E_ARG for dim < 2 or a hybrid below 10). */
+ * would, with no device and no library state (CUROB_E_ARG for dim < 2 and for the ids that
+ * initialize leaves undefined at dim, with the reason). */
 int curob_get_info(int fid, int comp, int *type, int *count, int *nseg);
 int curob_get_structure(int fid, int comp, double *o, int *perm, int *sizes, double *blocks, int *bases,
                         double *scale, double *offset);
