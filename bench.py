@@ -228,6 +228,10 @@ def secondary(torch, c, reps: int = 10) -> dict:
         x = torch.from_numpy(population(n, d, seed=0, dtype=np.float32)).to(dev)
         o = torch.empty(n, dtype=torch.float32, device=dev)
         per, per32, frac, frac32 = {}, {}, {}, {}
+        # one pass over every formula first: the device sat idle while the population was drawn,
+        # and the first function timed would otherwise carry the ramp back to full clocks
+        for fid in FIDS:
+            c.func_evaluatef(fid, x, out=o)
         for fid in FIDS:
             per[NAMES[fid]] = event_time_ms(torch, lambda: c.func_evaluatef(fid, x, out=o), reps)
         c.set_mode(c.MODE_FP32)
