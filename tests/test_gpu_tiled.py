@@ -812,3 +812,37 @@ def test_random_user_problems(env, chunk):
         else:
             allow = composition_allowance(orc, p, bases, x32w)
         check32(f, ref32, allow, tag)
+
+
+@pytest.mark.parametrize("dim, n, fids, fp64", [
+    (1000, 1_100_000, (11, 14), False),   # row-resident kernel, 4.4 GB of FP32 rows
+    (100, 11_000_000, (11, 16), False),   # resident kernel, 4.4 GB of FP32 rows
+    (100, 5_500_000, (11,), True),        # resident FP64 kernel, 4.4 GB of FP64 rows
+])
+def test_population_above_4_gib(env, dim, n, fids, fp64):
+    """Populations whose rows span more than 4 GiB (beyond a 32-bit byte offset and a buffer
+    resource's extent): sampled rows across the whole population, the last ones included,
+    against the oracle."""
+    c, orc, torch, use = env
+    from paper_1407_7737_amd.inputs import device_population
+    dt = torch.float64 if fp64 else torch.float32
+    assert n * dim * (8 if fp64 else 4) > 4 << 30
+    use(dim, maxc=n)
+    x = device_population(n, dim, seed=dim, dtype=dt, device="cuda")
+    out = torch.empty(n, dtype=dt, device="cuda")
+    rng = np.random.default_rng(dim)
+    idx = np.unique(np.concatenate([np.arange(64), rng.integers(0, n, size=2000),
+                                    np.arange(n - 2048, n)]))
+    xs = x[torch.from_numpy(idx).cuda()].double().cpu().numpy()
+    for fid in fids:
+        say(f"[4gib] dim={dim} n={n} fid={fid} fp64={fp64}")
+        p = orc.basic(fid, dim, SEED)
+        (c.func_evaluate if fp64 else c.func_evaluatef)(fid, x, out=out)
+        f = out[torch.from_numpy(idx).cuda()].double().cpu().numpy()
+        ref = p(xs, threads=16)
+        if fp64:
+            assert rel_err(f, ref).max() <= TOL64, (dim, fid)
+        else:
+            check32(f, ref, basic_allowance(orc, fid, p.shift(), p.rotation(), xs), ("4gib", dim, fid))
+    del x, out
+    torch.cuda.empty_cache()
