@@ -814,17 +814,20 @@ def test_random_user_problems(env, chunk):
         check32(f, ref32, allow, tag)
 
 
-@pytest.mark.parametrize("dim, n, fids, fp64", [
-    (1000, 1_100_000, (11, 14), False),   # row-resident kernel, 4.4 GB of FP32 rows
-    (100, 11_000_000, (11, 16), False),   # resident kernel, 4.4 GB of FP32 rows
-    (100, 5_500_000, (11,), True),        # resident FP64 kernel, 4.4 GB of FP64 rows
+@pytest.mark.parametrize("dim, n, fids, mode", [
+    (1000, 1_100_000, (11, 14, 25, 29), "split"),  # row-resident kernel, hybrid, composition: 4.4 GB of FP32 rows
+    (1000, 1_100_000, (11,), "fp32"),              # FP32-MFMA tiled kernels (65,536-row passes)
+    (1000, 550_000, (11,), "fp64"),                # FP64 tiled kernels, 4.4 GB of FP64 rows
+    (100, 11_000_000, (11, 16), "split"),          # resident kernel, 4.4 GB of FP32 rows
+    (100, 5_500_000, (11,), "fp64"),               # resident FP64 kernel, 4.4 GB of FP64 rows
 ])
-def test_population_above_4_gib(env, dim, n, fids, fp64):
+def test_population_above_4_gib(env, dim, n, fids, mode):
     """Populations whose rows span more than 4 GiB (beyond a 32-bit byte offset and a buffer
     resource's extent): sampled rows across the whole population, the last ones included,
     against the oracle."""
     c, orc, torch, use = env
     from paper_1407_7737_amd.inputs import device_population
+    fp64 = mode == "fp64"
     dt = torch.float64 if fp64 else torch.float32
     assert n * dim * (8 if fp64 else 4) > 4 << 30
     use(dim, maxc=n)
@@ -833,16 +836,30 @@ def test_population_above_4_gib(env, dim, n, fids, fp64):
     rng = np.random.default_rng(dim)
     idx = np.unique(np.concatenate([np.arange(64), rng.integers(0, n, size=2000),
                                     np.arange(n - 2048, n)]))
-    xs = x[torch.from_numpy(idx).cuda()].double().cpu().numpy()
+    tidx = torch.from_numpy(idx).cuda()
+    xs = x[tidx].double().cpu().numpy()
     for fid in fids:
-        say(f"[4gib] dim={dim} n={n} fid={fid} fp64={fp64}")
-        p = orc.basic(fid, dim, SEED)
-        (c.func_evaluate if fp64 else c.func_evaluatef)(fid, x, out=out)
-        f = out[torch.from_numpy(idx).cuda()].double().cpu().numpy()
+        say(f"[4gib] dim={dim} n={n} fid={fid} mode={mode}")
+        p = orc.fid_problem(fid, dim, SEED)
+        if fp64:
+            c.func_evaluate(fid, x, out=out)
+        else:
+            c.set_mode(c.MODE_FP32 if mode == "fp32" else c.MODE_SPLIT)
+            try:
+                c.func_evaluatef(fid, x, out=out)
+            finally:
+                c.set_mode(c.MODE_SPLIT)
+        f = out[tidx].double().cpu().numpy()
         ref = p(xs, threads=16)
         if fp64:
             assert rel_err(f, ref).max() <= TOL64, (dim, fid)
+            continue
+        if fid >= 29:
+            allow = composition_allowance(orc, p, COMPOSITION_G[fid], xs)
+        elif fid >= 23:
+            allow = hybrid_allowance(orc, p, HYBRID_BASES[fid], xs)
         else:
-            check32(f, ref, basic_allowance(orc, fid, p.shift(), p.rotation(), xs), ("4gib", dim, fid))
+            allow = basic_allowance(orc, fid, p.shift(), p.rotation(), xs)
+        check32(f, ref, allow, ("4gib", dim, fid, mode))
     del x, out
     torch.cuda.empty_cache()
