@@ -10,7 +10,8 @@ the dominant kernel (D*4 bytes read + 4 bytes written per row).
 
 Secondary workloads (reported under "secondary", not in "value"): the D = 1000, N = 2^18 form
 of the same eight formulas; a hybrid and a composition at D = 1000, N = 16384; 64 batched
-populations in one persistent launch (graph replay, direct launch, one call per population).
+populations in one persistent launch (graph replay, direct launch, one call per population);
+50-row calls and DE generations; the host-pointer entry points with their PCIe transfers.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-secondary]
                     [--copy-probe]
@@ -333,7 +334,38 @@ def secondary(torch, c, reps: int = 10) -> dict:
     progress("secondary: 50-row latency and DE generations")
     out["latency_n50"] = latency_small(torch, c)
     out["de_n50"] = de_generations(torch, c)
+    progress("secondary: host entry points (PCIe included)")
+    out["host_entry_d100_n262144"] = host_entry(torch, c)
     return out
+
+
+def host_entry(torch, c, reps: int = 5) -> dict:
+    """The host-pointer entry points (h_func_evaluatef, h_func_evaluate) at D = 100, N = 2^18 on
+    rotated Rastrigin: copy to the device, evaluate, copy back and wait, so the rate includes
+    both PCIe transfers.  Inputs in pageable (numpy) and in pinned host memory.  A figure for
+    callers that hold their population on the host, never the headline value."""
+    import time
+    from paper_1407_7737_amd.inputs import population
+    d, n = 100, 1 << 18
+    res = {}
+    c.initialize(d, n, 0)
+    try:
+        x32 = population(n, d, seed=0, dtype=np.float32)
+        pinned = torch.empty((n, d), dtype=torch.float32, pin_memory=True)
+        pinned.copy_(torch.from_numpy(x32))
+        x64 = population(n, d, seed=0)
+        for name, arr, fn in (("fp32_pageable", x32, c.h_func_evaluatef),
+                              ("fp32_pinned", pinned.numpy(), c.h_func_evaluatef),
+                              ("fp64_pageable", x64, c.h_func_evaluate)):
+            fn(11, arr)
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fn(11, arr)
+            dt = (time.perf_counter() - t0) / reps
+            res[name] = {"ms": dt * 1e3, "evals_per_s": n / dt, "input_gb_per_s": arr.nbytes / dt / 1e9}
+    finally:
+        c.dispose()
+    return res
 
 
 def de_generations(torch, c, gens: int = 100) -> dict:
