@@ -46,6 +46,7 @@ typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 constexpr int kWaves = 8;
 constexpr int kThreads = 64 * kWaves;
 constexpr int kMW = 3;      // m-tiles of one block per wave pass (one B chunk feeds them all)
+constexpr int kMWWide = 4;  // the same for problems with a block of 25..32 m-tiles (hybrid groups)
 constexpr int kSlots = 8;   // per (wave, row) partial: s0 c0 s1 c1 s2 c2 product pad
 constexpr int kCB = 2;      // 16-row column blocks per tile
 constexpr int kRows = 16 * kCB;
@@ -315,7 +316,10 @@ struct NextRows {
 // (hybrids, composition components).  NT: bf16 terms per operand (2: three products, 3: six).
 // AHEAD: steps the rotation tiles are requested ahead of their products (registers permitting).
 // LEAN (the fused composition kernel, short of registers): the epilogue reads its tables itself.
-template <int NT, int KIND, int AHEAD, bool LEAN = false>
+// MW: m-tiles per wave and pass.  Every step costs its B production and barrier whatever the
+// m-tiles it feeds, so a block of 25..32 m-tiles (a wide hybrid group) takes one pass of four
+// per wave instead of two passes of three (the fourth slot is idle in smaller blocks).
+template <int NT, int KIND, int AHEAD, bool LEAN = false, int MW = kMW>
 __device__ __forceinline__ float eval_tile(const TiledProb &tp, float *s_rows, int S, const uint16_t *s_goff,
                                            const float *s_ohp, unsigned char *s_ring, float *s_red, int lane,
                                            int wave, const NextRows &nx) {
@@ -378,26 +382,26 @@ __device__ __forceinline__ float eval_tile(const TiledProb &tp, float *s_rows, i
     const bool pairseg = KIND >= 0 ? KindTraits<(KIND >= 0 ? KIND : 0)>::pairwise : sg.pairwise != 0;
     any_pairs = any_pairs || pairseg;
     const float prm = seg_param(sg);
-    const int npass = (mts + kPassMTiles - 1) / kPassMTiles;
+    const int npass = (mts + (kWaves * MW) - 1) / (kWaves * MW);
 
     for (int pass = 0; pass < npass; ++pass) {
       // this pass: m-tiles mbase + kWaves j of the block.  A slot past the block's m-tiles
       // repeats the last m-tile and is discarded (no branch splits the step: waves 4 apart
       // share a SIMD, and the fullest SIMD sets the pace anyway)
-      const int mbase = pass * kPassMTiles + wave;
-      int mt[kMW];
-      bool act[kMW];
+      const int mbase = pass * (kWaves * MW) + wave;
+      int mt[MW];
+      bool act[MW];
 #pragma unroll
-      for (int j = 0; j < kMW; ++j) {
+      for (int j = 0; j < MW; ++j) {
         act[j] = mbase + kWaves * j < mts;
         mt[j] = act[j] ? mbase + kWaves * j : mts - 1;
       }
       // the epilogue's per-position tables, read now: no global load follows the next tile's
       // row requests, whose completion a later load would otherwise wait for
-      f32x4 cz4[kMW], cf4[kMW];
+      f32x4 cz4[MW], cf4[MW];
       auto read_epi = [&]() {
 #pragma unroll
-        for (int j = 0; j < kMW; ++j) {
+        for (int j = 0; j < MW; ++j) {
           const int pm = blk.x + 16 * mt[j] + 4 * q;  // 4 consecutive packed positions
           cz4[j] = *reinterpret_cast<const f32x4 *>(czp + pm);
           cf4[j] = *reinterpret_cast<const f32x4 *>(cfp + pm);
@@ -405,24 +409,24 @@ __device__ __forceinline__ float eval_tile(const TiledProb &tp, float *s_rows, i
       };
       if constexpr (!LEAN) read_epi();
       // rotation tiles through buffer loads: per-lane offset fixed, tile offset scalar
-      auto load_a = [&](bf16x8 (&au)[kMW][NT], int c) {
+      auto load_a = [&](bf16x8 (&au)[MW][NT], int c) {
 #pragma unroll
-        for (int j = 0; j < kMW; ++j) {
+        for (int j = 0; j < MW; ++j) {
           const int toff = (blk.z + mt[j] * nst + c) * (NT * 1024);
 #pragma unroll
           for (int u = 0; u < NT; ++u)
             au[j][u] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(qrs, lane * 16 + u * 1024, toff, 0));
         }
       };
-      f32x4 acc[kMW][kCB];
+      f32x4 acc[MW][kCB];
 #pragma unroll
-      for (int j = 0; j < kMW; ++j)
+      for (int j = 0; j < MW; ++j)
 #pragma unroll
         for (int cb = 0; cb < kCB; ++cb) acc[j][cb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
       // rotation tiles kAhead steps ahead: register set k holds the steps c with c % kAhead == k
       // (the loads of a step are in flight while the kAhead - 1 steps before it compute)
       constexpr int kAhead = AHEAD;
-      bf16x8 ar[kAhead][kMW][NT];
+      bf16x8 ar[kAhead][MW][NT];
 #pragma unroll
       for (int k = 0; k < kAhead; ++k) load_a(ar[k], k < nst ? k : nst - 1);
       // B operand pipeline (one barrier per step): step c consumes ring slot c & 1, gathers the
@@ -440,7 +444,7 @@ __device__ __forceinline__ float eval_tile(const TiledProb &tp, float *s_rows, i
       go = *reinterpret_cast<const uint32_t *>(s_goff + pos(1));
       oo = *reinterpret_cast<const f32x2 *>(s_ohp + pos(1));
       __syncthreads();
-      auto step = [&](int c, bf16x8 (&au)[kMW][NT]) {
+      auto step = [&](int c, bf16x8 (&au)[MW][NT]) {
         const unsigned char *slot = s_ring + (c & 1) * kSlot;
         bf16x8 bt[kCB][NT];
 #pragma unroll
@@ -452,12 +456,12 @@ __device__ __forceinline__ float eval_tile(const TiledProb &tp, float *s_rows, i
         const uint32_t go2 = *reinterpret_cast<const uint32_t *>(s_goff + pos(c + 2));
         const f32x2 oo2 = *reinterpret_cast<const f32x2 *>(s_ohp + pos(c + 2));
         __builtin_amdgcn_sched_barrier(0);
-        // the product stages outermost: kMW * kCB independent accumulators between two
+        // the product stages outermost: MW * kCB independent accumulators between two
         // products into the same one
 #pragma unroll
         for (int st = 0; st < (NT == 3 ? 6 : 3); ++st)
 #pragma unroll
-          for (int j = 0; j < kMW; ++j)
+          for (int j = 0; j < MW; ++j)
 #pragma unroll
             for (int cb = 0; cb < kCB; ++cb) acc[j][cb] = product_stage<NT>(st, au[j], bt[cb], acc[j][cb]);
         // this register set now takes step c + kAhead (clamped: past the end it reloads the last)
@@ -485,7 +489,7 @@ __device__ __forceinline__ float eval_tile(const TiledProb &tp, float *s_rows, i
       // the position's variable for pair terms (padding: z = 0 into the zero slot, unchanged)
       if constexpr (LEAN) read_epi();
 #pragma unroll
-      for (int j = 0; j < kMW; ++j) {
+      for (int j = 0; j < MW; ++j) {
         if (!act[j]) continue;
         const int pm = blk.x + 16 * (mbase + kWaves * j) + 4 * q;  // 4 consecutive packed positions
         if (pairseg) {
@@ -559,8 +563,10 @@ __device__ __forceinline__ void load_tables(const TiledProb &tp, uint16_t *s_gof
   }
 }
 
-// Basic function or hybrid: persistent grid over tiles of 32 rows.
-template <int NT, int KIND>
+// Basic function or hybrid: persistent grid over tiles of 32 rows.  MW: m-tiles per wave and
+// pass (kMWWide for a block of 25..32 m-tiles, with the rotation tiles one step less ahead to
+// stay within the registers).
+template <int NT, int KIND, int MW = kMW>
 __global__ __launch_bounds__(kThreads) void k_rowres(TiledProb tp, const float *__restrict__ x, int n,
                                                      float *__restrict__ out, int wide) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -584,7 +590,8 @@ __global__ __launch_bounds__(kThreads) void k_rowres(TiledProb tp, const float *
     finish_rows(D, S, s_rows);
     const int next = tile + static_cast<int>(gridDim.x);
     const NextRows nx{x, next < ntiles && !tp.any_pairwise ? next * kRows : -1, n, D, wide != 0};
-    const float F = eval_tile<NT, KIND, NT == 2 ? 4 : 3>(tp, s_rows, S, s_goff, s_ohp, s_ring, s_red, lane, wave, nx);
+    constexpr int kAheadSteps = (NT == 2 ? 4 : 3) - (MW > kMW ? 1 : 0);
+    const float F = eval_tile<NT, KIND, kAheadSteps, false, MW>(tp, s_rows, S, s_goff, s_ohp, s_ring, s_red, lane, wave, nx);
     requested = nx.row0 >= 0;
     if (wave == 0 && lane < kRows && row0 + lane < n) out[row0 + lane] = F + static_cast<float>(tp.bias);
   }

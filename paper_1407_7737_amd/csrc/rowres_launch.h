@@ -24,8 +24,12 @@ hipError_t launch_path(int kind_hint, const TiledProb &tp, const void *x, void *
                        hipStream_t st, std::integer_sequence<int, Ks...>) {
   constexpr int NT = split_terms(P);
   static const void *const basic[] = {reinterpret_cast<const void *>(&k_rowres<NT, Ks>)...};
+  // a block of 25..32 m-tiles (a wide hybrid group; basic blocks stay below) takes one pass of
+  // four m-tiles per wave instead of two of three
+  const bool wide_block = tp.mtiles_max > kPassMTiles && tp.mtiles_max <= kWaves * kMWWide;
   const void *fn = (kind_hint >= 0 && kind_hint < K_COUNT) ? basic[kind_hint]
-                                                           : reinterpret_cast<const void *>(&k_rowres<NT, -1>);
+                   : wide_block ? reinterpret_cast<const void *>(&k_rowres<NT, -1, kMWWide>)
+                                : reinterpret_cast<const void *>(&k_rowres<NT, -1>);
   const Carve L = carve(tp.Dp, tp.S, NT);
   if (L.total > kMaxLdsBytes || tp.D > kMaxD) return hipErrorInvalidValue;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, L.total);

@@ -63,6 +63,7 @@ struct TiledProb {
   int D, Dp, nblocks, ngroups, nsegs;
   int any_pairwise;
   int pair_mtiles_max;  // m-tiles of the largest rotation block with pair terms (host use)
+  int mtiles_max;       // m-tiles of the largest rotation block (host use)
   int qfrag_kib;        // size of the rotation tiles in KiB (host use)
   int rowwise;    // unrotated basic problem: z = s (x - o) + c' per variable, no MFMA work
   double scale0;  // s of that problem

@@ -209,9 +209,12 @@ hipError_t build_tiled(const Problem &p, int path, TiledDev &td, std::string &er
   tp.bias = p.fopt;
   tp.any_pairwise = 0;
   tp.pair_mtiles_max = 0;
-  for (size_t b = 0; b < blocks.size(); ++b)
+  tp.mtiles_max = 0;
+  for (size_t b = 0; b < blocks.size(); ++b) {
+    tp.mtiles_max = std::max(tp.mtiles_max, ceil32(blocks[b].n) / 16);
     if (kind_is_pairwise(fn_spec(p.segs[hybrid ? blocks[b].seg : 0].base).kind))
       tp.pair_mtiles_max = std::max(tp.pair_mtiles_max, ceil32(blocks[b].n) / 16);
+  }
   // unrotated basic problems: the identity blocks of 32 keep packed position = variable, and
   // the row-wise kernel reads the per-position tables by variable
   tp.rowwise = (!hybrid && !rotate) ? 1 : 0;
