@@ -4,13 +4,15 @@
 //
 // A workgroup of eight waves holds 32 population rows in LDS (x as read) and computes every
 // output of the packed block-diagonal rotation for them:
-//   - for each rotation block, each wave takes up to three m-tiles (16 outputs) of the block and
-//     all waves walk the block's k steps together.  The B operand of a k step (y = x - o_hi at
+//   - for each rotation block, each wave takes up to three m-tiles (16 outputs) of the block per
+//     pass (four when a block has 25..32 m-tiles, so that it takes one pass) and all waves walk
+//     the block's k steps together.  The B operand of a k step (y = x - o_hi at
 //     32 packed positions for the 32 rows, cut into bf16 terms) is produced once per workgroup,
 //     one pair of positions of one row per thread, into a two-slot LDS ring in MFMA operand
 //     order, one barrier per step; every wave then reads it with one 16-byte LDS read per
 //     (column block, term).  The rotation tiles (A operand) stream from L2 through buffer loads
-//     issued several steps ahead of their products (four for three products, three for six);
+//     issued several steps ahead of their products (four for three products, three for six,
+//     one less with four m-tiles per wave);
 //   - z = acc + c' then the formula's per-element terms go into the wave's compensated row
 //     sums.  Formulas with pair terms instead write z back into the LDS rows, at the slot of
 //     the position's own variable (the block's variables are read by no later step), and the
